@@ -1,0 +1,276 @@
+"""Problem descriptions and seeded synthetic initial states.
+
+This module holds no arithmetic of the solver: it states a problem (grid,
+material constants of Eq. (7), boundary conditions, the interface profiles of
+Eqs. (61)-(62)) and produces the initial primitive fields (T, F_l, C, u, v, p)
+as float64 planes of shape (ny, nx), row-major with x fastest.  The GPU
+library and the CPU oracle each turn these into the conserved vector of
+Eq. (49) with their own code.
+
+Lattice units: the cell size is 1 unless ``dx`` says otherwise, the streaming
+step ``delta_t`` is dx/2 (the largest value that keeps the surrounding points
+of Eq. (54) inside the two cells sharing the face) and the update step ``dt``
+is fixed for a run (Sec. 2.4, text after Eq. 58).
+
+The configurations follow the paper's benchmark problems (Sec. 3.1-3.5) in
+nondimensional form: melting temperature 0, cold wall -1, C_p = 1,
+L = C_p (T_m - T_w) / Ste (Stefan number as defined in Sec. 3.2), liquid
+density 1, interface width xi = 4 cells (Eq. 61), Q_g = 1, M_c = 0.1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+NOSLIP, FREESLIP, OUTLET = 0, 1, 2
+ADIABATIC, DIRICHLET = 0, 1
+SIDES = ("x-", "x+", "y-", "y+")
+
+
+@dataclass
+class Wall:
+    """One non-periodic side: flow rule, heat rule, wall temperature, contact angle."""
+
+    flow: int = NOSLIP
+    heat: int = ADIABATIC
+    T_w: float = 0.0
+    theta_deg: float = 90.0
+
+
+@dataclass
+class Problem:
+    nx: int
+    ny: int
+    dx: float = 1.0
+    lattice_hg: int = 9
+    delta_t: float = 0.5
+    dt: float = 0.5
+    # (solid, liquid, gas) for Eq. (7)
+    rho: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    mu: Tuple[float, float, float] = (0.01, 0.01, 0.01)
+    lam: Tuple[float, float, float] = (0.4, 0.4, 0.4)
+    cp: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    latent: float = 10.0
+    T_s: float = 0.0
+    T_l: float = 0.0
+    sigma: float = 0.0
+    xi: float = 4.0
+    mobility: float = 0.1
+    Qg: float = 1.0
+    gx: float = 0.0
+    gy: float = 0.0
+    surf_model: int = 0
+    periodic_x: bool = False
+    periodic_y: bool = False
+    walls: Dict[str, Wall] = field(default_factory=dict)
+    precision: int = 0  # 0: FP64; 1: FP32 fields and fluxes with FP64 enthalpy
+
+    def wall(self, side: str) -> Optional[Wall]:
+        periodic = self.periodic_x if side[0] == "x" else self.periodic_y
+        if periodic:
+            return None
+        return self.walls.get(side, Wall())
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+
+@dataclass
+class InitialState:
+    """Primitive initial fields, each float64 of shape (ny, nx)."""
+
+    T: np.ndarray
+    Fl: np.ndarray
+    C: np.ndarray
+    u: np.ndarray
+    v: np.ndarray
+    p: np.ndarray
+
+    def planes(self):
+        return [np.ascontiguousarray(a, dtype=np.float64) for a in (self.T, self.Fl, self.C, self.u, self.v, self.p)]
+
+
+def cell_centres(pr: Problem):
+    x = (np.arange(pr.nx) + 0.5) * pr.dx
+    y = (np.arange(pr.ny) + 0.5) * pr.dx
+    return np.meshgrid(x, y)  # (ny, nx) each
+
+
+def layer_profile(coord: np.ndarray, H0: float, xi: float) -> np.ndarray:
+    """Eq. (61): condensed phase below coord = H0."""
+    return 0.5 * (1.0 + np.tanh(2.0 * (H0 - coord) / xi))
+
+
+def droplet_profile(X, Y, x0, y0, R, xi):
+    """Eq. (62) with the distance to the centre (the printed form lacks the square root)."""
+    r = np.sqrt((X - x0) ** 2 + (Y - y0) ** 2)
+    return 0.5 * (1.0 + np.tanh(2.0 * (R - r) / xi))
+
+
+def uniform_state(pr: Problem, T0: float = 0.0, Fl0: float = 1.0, C0: float = 1.0) -> InitialState:
+    shape = (pr.ny, pr.nx)
+    return InitialState(
+        T=np.full(shape, T0), Fl=np.full(shape, Fl0), C=np.full(shape, C0),
+        u=np.zeros(shape), v=np.zeros(shape), p=np.zeros(shape),
+    )
+
+
+def counter_uniform(seed: int, shape) -> np.ndarray:
+    """Seeded uniform numbers in [-1, 1), keyed by (seed, j, i)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, shape[0], shape[1]]))
+    return rng.uniform(-1.0, 1.0, size=shape)
+
+
+def seeded_fields(pr: Problem, seed: int, amp: float = 1.0) -> InitialState:
+    """Smooth random primitive fields for parity checks (not a physical state)."""
+    rng = np.random.default_rng(seed)
+    X, Y = cell_centres(pr)
+    Lx, Ly = pr.nx * pr.dx, pr.ny * pr.dx
+
+    def smooth(a0, a1):
+        out = np.full(X.shape, a0)
+        for _ in range(3):
+            kx, ky = rng.integers(1, 3, size=2)
+            ph = rng.uniform(0, 2 * np.pi, size=2)
+            out = out + a1 * rng.uniform(-1, 1) * np.sin(2 * np.pi * kx * X / Lx + ph[0]) * np.cos(
+                2 * np.pi * ky * Y / Ly + ph[1])
+        return out
+
+    C = np.clip(smooth(0.5, 0.35 * amp) + 0.02 * amp * rng.uniform(-1, 1, X.shape), -0.02, 1.02)
+    T = smooth(0.0, 0.6 * amp) + 0.05 * amp * rng.uniform(-1, 1, X.shape)
+    Fl = np.clip(smooth(0.5, 0.6), 0.0, 1.0)
+    u = smooth(0.0, 0.03 * amp)
+    v = smooth(0.0, 0.03 * amp)
+    p = smooth(0.0, 0.01 * amp)
+    return InitialState(T=T, Fl=Fl, C=C, u=u, v=v, p=p)
+
+
+# ---------------------------------------------------------------------------
+# Benchmark configurations (nondimensional, lattice units)
+# ---------------------------------------------------------------------------
+RHO_G = 1e-3  # gas / liquid density ratio 1/1000
+
+
+def _gas_lambda(lam_l: float, rho_g: float) -> float:
+    # gas thermal diffusivity equal to the liquid's (the paper gives no gas data)
+    return lam_l * rho_g
+
+
+def _gas_mu(mu_l: float, rho_g: float) -> float:
+    # gas kinematic viscosity equal to the liquid's; a gas at 1/1000 of the
+    # liquid density with 1/100 of its viscosity would need a smaller update step
+    return mu_l * rho_g
+
+
+def conductive_freezing(nx: int = 128, ny: int = 4, ste: float = 0.1, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.1 in its one-phase form: liquid at the melting point, cold left wall
+    at -1, adiabatic right wall, periodic in y, no flow, C = 1 everywhere."""
+    pr = Problem(
+        nx=nx, ny=ny, rho=(1.0, 1.0, 1.0), mu=(0.01, 0.01, 0.01), lam=(0.4, 0.4, 0.4),
+        cp=(1.0, 1.0, 1.0), latent=1.0 / ste, periodic_y=True,
+        walls={"x-": Wall(NOSLIP, DIRICHLET, -1.0), "x+": Wall(NOSLIP, ADIABATIC)},
+    ).replace(**kw)
+    return pr, uniform_state(pr)
+
+
+def three_phase_stefan(nx: int = 256, ny: int = 8, H0: float = 128.0, ratio: float = 0.9,
+                       ste: float = 0.1, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.2 laid along x: cold wall at x = 0, liquid 0 < x < H0, gas beyond."""
+    rho_g = RHO_G
+    pr = Problem(
+        nx=nx, ny=ny, rho=(ratio, 1.0, rho_g), mu=(0.01, 0.01, 1e-4),
+        lam=(0.4, 0.4, _gas_lambda(0.4, rho_g)), cp=(1.0, 1.0, 1.0), latent=1.0 / ste,
+        sigma=0.01, periodic_y=True,
+        walls={"x-": Wall(NOSLIP, DIRICHLET, -1.0), "x+": Wall(NOSLIP, ADIABATIC)},
+    ).replace(**kw)
+    X, _ = cell_centres(pr)
+    st = uniform_state(pr)
+    st.C = layer_profile(X, H0, pr.xi)
+    return pr, st
+
+
+def film_freezing(n: int = 256, height: float = 0.3, ratio: float = 0.917, ste: float = 0.05,
+                  bond: float = 1.0, seed: int = 0, amp: float = 1e-3, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.3: film of height 0.3 n on a cold bottom wall in a closed box."""
+    rho_g = RHO_G
+    H0 = height * n
+    sigma = 0.01
+    g = bond * sigma / (1.0 * H0 * H0)
+    pr = Problem(
+        nx=n, ny=n, rho=(ratio, 1.0, rho_g), mu=(0.05, 0.05, _gas_mu(0.05, rho_g)),
+        lam=(0.4, 0.4, _gas_lambda(0.4, rho_g)), cp=(1.0, 1.0, 1.0), latent=1.0 / ste,
+        sigma=sigma, gy=-g,
+        walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0), "y+": Wall()},
+    ).replace(**kw)
+    _, Y = cell_centres(pr)
+    st = uniform_state(pr)
+    st.C = layer_profile(Y, H0, pr.xi)
+    st.T = amp * counter_uniform(seed, (pr.ny, pr.nx))
+    return pr, st
+
+
+def static_droplet(n: int = 512, R: float = 128.0, theta_deg: float = 90.0, ratio: float = 0.917,
+                   ste: float = 0.1, ca: float = 0.01, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.4: droplet resting on a cold bottom wall (a half disc for 90 deg)."""
+    rho_g = RHO_G
+    lam_l = 0.4
+    u_ref = lam_l / (1.0 * 1.0) / R  # thermal velocity alpha_l / R
+    mu_l = 0.05
+    sigma = mu_l * u_ref / ca
+    pr = Problem(
+        nx=n, ny=n, rho=(ratio, 1.0, rho_g), mu=(mu_l, mu_l, _gas_mu(mu_l, rho_g)),
+        lam=(lam_l, lam_l, _gas_lambda(lam_l, rho_g)), cp=(1.0, 1.0, 1.0), latent=1.0 / ste,
+        sigma=sigma,
+        walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0, theta_deg), "y+": Wall()},
+    ).replace(**kw)
+    X, Y = cell_centres(pr)
+    st = uniform_state(pr)
+    x0 = 0.5 * pr.nx * pr.dx
+    # circular cap of the same area as a half disc of radius R, meeting the wall at theta
+    th = math.radians(theta_deg)
+    Rc = R * math.sqrt((math.pi / 2.0) / (th - math.sin(th) * math.cos(th)))
+    y0 = -Rc * math.cos(th)
+    st.C = droplet_profile(X, Y, x0, y0, Rc, pr.xi)
+    return pr, st
+
+
+def impact_droplet(n: int = 256, we: float = 50.0, re: float = 500.0, U: float = 0.05,
+                   ratio: float = 0.917, ste: float = 0.1, supercool: float = 0.5,
+                   theta_deg: float = 90.0, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.5: droplet of diameter n/4 moving down onto a cold wall; the
+    surface tension acts on the unfrozen part only (surf_model 1)."""
+    rho_g = RHO_G
+    D = n / 4.0
+    sigma = 1.0 * U * U * D / we
+    mu_l = 1.0 * U * D / re
+    lam_l = 0.4
+    pr = Problem(
+        nx=n, ny=n, rho=(ratio, 1.0, rho_g), mu=(mu_l, mu_l, _gas_mu(mu_l, rho_g)),
+        lam=(lam_l, lam_l, _gas_lambda(lam_l, rho_g)), cp=(1.0, 1.0, 1.0), latent=1.0 / ste,
+        sigma=sigma, surf_model=1,
+        walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0, theta_deg), "y+": Wall()},
+    ).replace(**kw)
+    X, Y = cell_centres(pr)
+    st = uniform_state(pr)
+    x0 = 0.5 * pr.nx * pr.dx
+    y0 = 0.5 * D + 2.0 * pr.xi
+    st.C = droplet_profile(X, Y, x0, y0, 0.5 * D, pr.xi)
+    st.T = np.where(st.C > 0.5, -supercool, 0.0)
+    st.v = -U * st.C
+    return pr, st
+
+
+CONFIGS = {
+    "C1": lambda: conductive_freezing(),
+    "C2": lambda: three_phase_stefan(),
+    "C3": lambda: film_freezing(),
+    "C4": lambda: static_droplet(),
+}
