@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark of the EULBFS time step on one MI355X.
+
+Workload: the static-droplet freezing problem of Sec. 3.4 at 512 x 512 cells
+(droplet radius 128 on a cold wall, contact angle 90 deg, rho_s/rho_l = 0.917,
+gas/liquid density ratio 1/1000, Ste = 0.1, Ca = 0.01), synthetic initial
+state, FP64, fused flux + update kernel.  One step = one SSP-RK3 time step
+(three fused stage launches) over the whole grid.
+
+Prints one JSON line: cell updates per second (MLUPS), the roofline of the
+fused stage kernel (algorithmic HBM bytes per launch over its average launch
+time, measured with HIP events on the stream the kernels run on) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s (MLUPS) & % HBM BW; batched solves/s + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# compulsory HBM words per cell and time step (SSP-RK3 over the five conserved
+# planes and the dF_s/dt plane): stage 1 reads W^n and dF_s/dt and writes W1
+# (11), stage 2 reads W1, W^n, dF_s/dt and writes W2 (16), stage 3 reads W2,
+# W^n, dF_s/dt and writes W^{n+1} and dF_s/dt (17)
+WORDS_PER_CELL_STEP = 44
+
+
+def bytes_per_cell_step(precision: int) -> int:
+    if precision == 0:
+        return WORDS_PER_CELL_STEP * 8
+    # FP32 fields with the enthalpy plane in FP64: 11 of the 44 words are H
+    return 33 * 4 + 11 * 8
+
+
+def workload(name: str):
+    from paper_2507_03366_amd import problems as PB
+
+    if name == "C4":
+        pr, st = PB.static_droplet()
+        desc = ("static droplet freezing on a cold wall, 512x512 cells, R=128, theta=90deg, rho_s/rho_l=0.917, "
+                "rho_g/rho_l=1e-3, Ste=0.1, Ca=0.01")
+    elif name == "C3":
+        pr, st = PB.film_freezing()
+        desc = "liquid film freezing, 256x256 cells, film height 0.3, Bo=1, Ste=0.05, rho_s/rho_l=0.917"
+    elif name == "C2":
+        pr, st = PB.three_phase_stefan()
+        desc = "three-phase Stefan problem, 256x8 cells, rho_s/rho_l=0.9, rho_g/rho_l=1e-3, Ste=0.1"
+    elif name.startswith("R"):
+        n = int(name[1:])
+        pr, st = PB.static_droplet(n=n, R=n / 4)
+        pr = pr.replace(sigma=PB.static_droplet()[0].sigma)
+        desc = f"static droplet freezing scaled to {n}x{n} cells (R={n // 4}), same material constants as 512x512"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return pr, st, desc
+
+
+def cpu_baseline(pr, st, budget_s: float):
+    """Time the FP64 oracle as it stands on this host's cores."""
+    from oracle import oracle as O
+
+    O.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+    import numpy as np
+
+    W = O.init(pr, st)
+    fs = np.zeros((pr.ny, pr.nx))
+    t0 = time.perf_counter()
+    W, fs = O.step(pr, W, fs, 1)
+    t1 = time.perf_counter()
+    steps = 1
+    more = int(max(0.0, budget_s - (t1 - t0)) / max(t1 - t0, 1e-6))
+    if more > 0:
+        W, fs = O.step(pr, W, fs, more)
+        steps += more
+    el = time.perf_counter() - t0
+    return {"value": pr.cells * steps / el / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} oracle steps of the same {pr.nx}x{pr.ny} workload from its initial state, "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="C4")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--kernel", default="fused", choices=["fused", "split"])
+    ap.add_argument("--tile", default="0x0")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run is not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2507_03366_amd import eulbfs as E
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    pr, st, desc = workload(args.workload)
+    precision = 0 if args.precision == "fp64" else 1
+    kernel = E.KERNEL_FUSED if args.kernel == "fused" else E.KERNEL_SPLIT
+    tile = tuple(int(v) for v in args.tile.split("x"))
+    stream = torch.cuda.current_stream()
+    s = E.Solver(pr, st, precision=precision, kernel=kernel, tile=tile, stream=stream)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    diag = s.diagnostics()
+    s.close()
+    if diag["nonfinite"] != 0:
+        raise SystemExit("state became non-finite during the benchmark")
+
+    cells = pr.cells
+    mlups = cells * args.steps / (ms * 1e-3) / 1e6
+    launches = 3 * args.steps if kernel == E.KERNEL_FUSED else 12 * args.steps
+    avg_launch_us = ms * 1e3 / launches
+    bpcs = bytes_per_cell_step(precision)
+    alg_bytes_per_launch = bpcs * cells / 3.0
+    achieved = alg_bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32+f64H",
+        "data": "synthetic",
+        "config": {"workload": desc, "nx": pr.nx, "ny": pr.ny, "precision": args.precision,
+                   "kernel": args.kernel, "tile": args.tile, "steps_are": "SSP-RK3 time steps"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_stage_fused" if kernel == E.KERNEL_FUSED else "split stage (4 kernels)",
+                     "avg_launch_us": round(avg_launch_us, 2),
+                     "alg_bytes_per_launch": int(alg_bytes_per_launch),
+                     "bytes_per_cell_step": bpcs},
+        "diagnostics_after": {k: float(v) for k, v in diag.items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pr, st, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

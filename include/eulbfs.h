@@ -1,0 +1,211 @@
+/*
+ * eulbfs.h -- C ABI of the MI355X (gfx950) EULBFS time-step library.
+ *
+ * EULBFS: enthalpy-based unified lattice Boltzmann flux solver for liquid
+ * solidification with volume change (Zhou, Yang, Wang, Wu, Niu; arXiv
+ * 2507.03366).  One time step advances the conserved vector
+ *     W = (H, p, rho c_s^2 u, rho c_s^2 v, C)                        (Eq. 49)
+ * of the cell-centred finite-volume form dW/dt = -div F + F_E (Eqs. 48-52)
+ * with the SSP-RK3 scheme of Eq. (58).  The face fluxes F (Eq. 53) come from
+ * a local lattice Boltzmann reconstruction at each face (Sec. 2.4, Eqs.
+ * 54-56): D2Q9 for the flow field, D2Q9 or D2Q5 for the total enthalpy and
+ * the phase field.  After each stage the enthalpy closure H -> (T, F_l)
+ * (Eqs. 5-6) and the mixture rule (Eq. 7) give the primitive fields; the
+ * expansion source rho c_s^2 (1 - rho_s/rho_l) dF_s/dt (Eq. 26) and its
+ * companions (Eqs. 27, 40, 51) couple solidification to the flow.
+ *
+ * Conventions
+ *   - Lattice units: cell size dx (default 1), c_s^2 = 1/3, streaming step
+ *     delta_t with 0 < delta_t <= dx/2, fixed update step dt.
+ *   - Fields are planes of nx*ny values, row-major, x fastest (index
+ *     j*nx + i, cell centre ((i+1/2) dx, (j+1/2) dx)).
+ *   - Every function returns EULBFS_OK (0) or a negative status; the text of
+ *     the last failure is returned by eulbfs_last_error().
+ *   - A handle is used by one host thread at a time.  All device work is
+ *     enqueued on the stream given at creation (NULL: the default stream).
+ *   - Device memory: the caller may pass a workspace of at least
+ *     eulbfs_workspace_bytes() bytes (for example a torch uint8 tensor); the
+ *     library then allocates no device memory for the state.  With a NULL
+ *     workspace the library allocates and frees its own.
+ *   - The readings of the paper that this library implements where the text
+ *     is silent or garbled are listed with the parameter struct below.
+ */
+#ifndef EULBFS_H
+#define EULBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EULBFS_ABI_VERSION 1u
+
+/* status codes */
+#define EULBFS_OK 0
+#define EULBFS_EINVAL (-1)    /* bad argument or parameter                        */
+#define EULBFS_ENOMEM (-2)    /* workspace too small or allocation failed         */
+#define EULBFS_EDEVICE (-3)   /* a HIP call failed                                */
+#define EULBFS_EUNSTABLE (-4) /* NaN/Inf in the state; the handle stays poisoned  */
+#define EULBFS_EBUSY (-5)     /* no free slot / HBM budget (batch API)            */
+#define EULBFS_ENOTSUP (-6)   /* valid request this build does not provide        */
+
+/* boundary rules for a wall side (Secs. 3.1-3.5 state them at the continuous
+ * level; the discrete rules are the three-layer ghost ring described below) */
+#define EULBFS_FLOW_NOSLIP 0   /* both momentum components odd               */
+#define EULBFS_FLOW_FREESLIP 1 /* normal odd, tangential even (symmetry)     */
+#define EULBFS_FLOW_OUTLET 2   /* both even (zero gradient); mass may leave  */
+#define EULBFS_HEAT_ADIABATIC 0
+#define EULBFS_HEAT_DIRICHLET 1 /* cold surface at T_w                       */
+
+#define EULBFS_FP64 0 /* FP64 fields and arithmetic                                     */
+#define EULBFS_FP32 1 /* FP32 fields and flux arithmetic; H stored and accumulated in FP64 */
+
+#define EULBFS_KERNEL_FUSED 0 /* one fused flux + update kernel per RK stage      */
+#define EULBFS_KERNEL_SPLIT 1 /* ghost fill, primitives, face fluxes, update apart */
+
+/* One side of the domain.  Sides are indexed 0: x-, 1: x+, 2: y-, 3: y+.
+ * periodic must agree on opposite sides.  For a wall:
+ *   ghost layer k = 1..3 mirrors interior layer k-1; pressure even; momentum
+ *   by `flow`; H even (adiabatic) or, for a Dirichlet wall, T_g = 2 T_w -
+ *   T_mirror and H_g from the inverse of Eqs. (5)-(6); wetting C_g = C_mirror
+ *   + (2k-1) dx (4/xi) cos(theta) C_w (1 - C_w), with C_w the first interior
+ *   cell (theta = 90 deg is a plain no-flux mirror).  On the wall face the
+ *   mass flux is 0 (unless outlet), the phase-field flux is 0 and the heat
+ *   flux is 0 when adiabatic. */
+typedef struct {
+    int32_t periodic;
+    int32_t flow;
+    int32_t heat;
+    int32_t reserved;
+    double T_w;       /* EULBFS_HEAT_DIRICHLET wall temperature           */
+    double theta_deg; /* equilibrium contact angle through the liquid, deg */
+} eulbfs_bc;
+
+/* Problem parameters (all in lattice units).
+ * Readings of the paper implemented by this library:
+ *   - D2Q9 weights 4/9, 1/9, 1/36; D2Q5 weights 1/3, 1/6; c_s^2 = 1/3.
+ *   - f* = f^eq(x_f) + (1 - 1/(2 tau_f)) f^neq-m (Eq. 37 prints '-').
+ *   - mu_c = 2 beta C(C-1)(2C-1) - kappa lap C, beta = 12 sigma/xi,
+ *     kappa = 3 xi sigma/2 (Sec. 2.3.1 prints '+ kappa').
+ *   - f^eq-m (Eqs. 33-34): f^eq with the old-level face density, without the
+ *     leading 1 of Gamma.
+ *   - C source C (1 - rho_s/rho_l) dF_s/dt kept in row 5 of F_E (Eqs. 40, 47).
+ *   - C_p,ref = (C_p,s + C_p,l)/2; H = C_p T + L F_l in all phases; the solid
+ *     fraction entering Eq. (7) is F_s = C (1 - F_l); C and F_s clamped to
+ *     [0, 1] where they enter Eq. (7) or the closure.
+ *   - central gradients, 5-point Laplacian, points on the face average both
+ *     sides' extrapolations (Eq. 54), old-level face values are the average
+ *     of both sides' extrapolations to the face centre.
+ *   - dF_s/dt lagged by one step; momentum projected M <- (1 - F_s) M after
+ *     each RK stage (rigid solid, Eq. 25).
+ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(eulbfs_params)                       */
+    uint32_t abi_version; /* EULBFS_ABI_VERSION                          */
+    int32_t nx, ny;       /* cells; >= 4 each                            */
+    int32_t lattice_hg;   /* 9 (paper) or 5: lattice of h and g          */
+    int32_t precision;    /* EULBFS_FP64 or EULBFS_FP32                  */
+    int32_t kernel;       /* EULBFS_KERNEL_FUSED or EULBFS_KERNEL_SPLIT  */
+    int32_t surf_model;   /* 0: F_surf = -C grad mu_c (Sec. 2.4)
+                             1: F_surf = -F_l C grad mu_c (Sec. 3.5)     */
+    double dx;            /* cell size                                   */
+    double delta_t;       /* streaming step (Sec. 2.5 step 1)            */
+    double dt;            /* update step of Eq. (58)                     */
+    double rho[3], mu[3], lambda[3], cp[3]; /* [solid, liquid, gas], Eq. (7) */
+    double latent;        /* L                                           */
+    double T_s, T_l;      /* solidus, liquidus (Eqs. 5-6); T_s <= T_l    */
+    double sigma, xi;     /* surface tension, interface width            */
+    double mobility, Qg;  /* M_c and Q_g of Eq. (41): tau_g = 1/2 + M_c/(Q_g delta_t) */
+    double gx, gy;        /* gravity; G = rho g in Eq. (51)              */
+    eulbfs_bc bc[4];
+    int32_t tile_x, tile_y; /* fused-kernel tile; 0 picks the default    */
+    int32_t reserved[6];
+} eulbfs_params;
+
+/* Initial state. */
+#define EULBFS_INIT_PRIMITIVE 0 /* 6 planes: T, F_l, C, u, v, p                */
+#define EULBFS_INIT_CONSERVED 1 /* 6 planes: H, p, Mx, My, C, dF_s/dt (restart) */
+typedef struct {
+    int32_t kind;
+    int32_t on_device;   /* 1: planes point to device memory             */
+    const double* planes; /* 6 * nx * ny doubles, plane after plane       */
+} eulbfs_init;
+/* EULBFS_INIT_PRIMITIVE: H = (1 - F_l)(H_s + C_p^S (T - T_s)) + F_l (H_l +
+ * C_p^L (T - T_l)) with H_s = C_p^S T_s, H_l = C_p^L T_l + L (so a liquid
+ * given below T_m recalesces to the heat-balance state of Sec. 3.4), and
+ * M = rho c_s^2 (u, v) with rho from Eq. (7) after the closure of that H.
+ * The planes are copied before eulbfs_create returns. */
+
+/* Field and scalar selectors for eulbfs_query / eulbfs_set_field.
+ * Fields: nx*ny doubles (converted from FP32 storage when precision is FP32). */
+#define EULBFS_FIELD_H 0
+#define EULBFS_FIELD_P 1
+#define EULBFS_FIELD_MX 2
+#define EULBFS_FIELD_MY 3
+#define EULBFS_FIELD_C 4
+#define EULBFS_FIELD_FSDOT 5 /* lagged dF_s/dt                                 */
+#define EULBFS_FIELD_T 6
+#define EULBFS_FIELD_FL 7
+#define EULBFS_FIELD_FS 8
+#define EULBFS_FIELD_RHO 9
+#define EULBFS_FIELD_U 10
+#define EULBFS_FIELD_V 11
+#define EULBFS_FIELD_MUC 12
+#define EULBFS_FIELD_W_ALL 13    /* 6 planes: H, p, Mx, My, C, dF_s/dt (checkpoint) */
+#define EULBFS_FIELD_W_GHOSTED 14 /* 5 planes of (nx+6)*(ny+6): state with its ghost ring */
+/* Scalars: EULBFS_SCALAR_DIAG fills EULBFS_NDIAG doubles:
+ *   [0] sum rho dV, [1] sum C dV, [2] sum H dV, [3] sum F_s dV, [4] max |u|,
+ *   [5] non-finite cell count, [6] sum_j F_s(nx/2, j) dx (tip height on the
+ *   middle column), [7] time, [8] steps taken, [9] dt
+ * The sums are FP64 and deterministic (fixed two-pass order, no atomics). */
+#define EULBFS_SCALAR_DIAG 100
+#define EULBFS_NDIAG 10
+
+/* Host-only: validate parameters.  msg (may be NULL) receives the reason. */
+int eulbfs_check_params(const eulbfs_params* prm, char* msg, size_t msg_len);
+
+/* Host-only: bytes of device workspace a solver with these parameters needs
+ * (0 if the parameters are invalid). */
+size_t eulbfs_workspace_bytes(const eulbfs_params* prm);
+
+/* Create a solver: validates prm, carves the workspace (d_ws, ws_bytes) or
+ * allocates one (d_ws == NULL), writes the initial state.  hip_stream is a
+ * hipStream_t (NULL: default stream).  On failure *out is NULL. */
+int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes,
+                  void* hip_stream, struct eulbfs_solver** out);
+typedef struct eulbfs_solver* eulbfs_t;
+
+/* Enqueue nsteps SSP-RK3 steps (Eq. 58); asynchronous. */
+int eulbfs_step(eulbfs_t h, int64_t nsteps);
+
+/* eulbfs_step, then synchronise the stream and check the state: returns
+ * EULBFS_EUNSTABLE (and poisons the handle) if any cell is non-finite. */
+int eulbfs_run(eulbfs_t h, int64_t nsteps);
+
+/* Read a field (EULBFS_FIELD_*) or the diagnostics (EULBFS_SCALAR_DIAG) into
+ * out (bytes large enough; host memory unless out_on_device).  Synchronises. */
+int eulbfs_query(eulbfs_t h, int32_t what, void* out, size_t bytes, int32_t out_on_device);
+
+/* Overwrite one conserved plane (FIELD_H..FIELD_FSDOT) or all six
+ * (FIELD_W_ALL) from nx*ny doubles per plane.  Synchronises. */
+int eulbfs_set_field(eulbfs_t h, int32_t what, const void* in, size_t bytes, int32_t in_on_device);
+
+/* Evaluate the residual R(W) of Eq. (57) for the current state with the
+ * split kernels: R (5 planes nx*ny), Fx (5 planes (nx+1)*ny, face i at
+ * x = i dx), Fy (5 planes nx*(ny+1), face j at y = j dx); any may be NULL.
+ * Doubles, host memory unless on_device.  Synchronises. */
+int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device);
+
+/* Release a solver; NULL is accepted. */
+int eulbfs_destroy(eulbfs_t h);
+
+/* Text of the last failure on this handle (or, for h == NULL, of the last
+ * failure of a create or host-only call on this thread). */
+const char* eulbfs_last_error(eulbfs_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EULBFS_H */

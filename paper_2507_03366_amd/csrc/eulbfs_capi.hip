@@ -1,0 +1,576 @@
+// C-ABI runtime of the EULBFS library: parameter validation, workspace
+// layout, stage sequencing on the caller's stream, queries and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/eulbfs.h"
+#include "eulbfs_internal.h"
+
+using namespace eulbfs;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+inline int round_pitch(int n) { return (n + 63) / 64 * 64; }
+
+int set_err(std::string* where, int code, const std::string& msg)
+{
+    if (where) *where = msg;
+    g_thread_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return set_err(err, EULBFS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+std::string check(const eulbfs_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->struct_size != sizeof(eulbfs_params)) return "struct_size does not match sizeof(eulbfs_params)";
+    if (p->abi_version != EULBFS_ABI_VERSION) return "abi_version mismatch";
+    if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return "grid too large";
+    if (!(p->dx > 0)) return "dx must be > 0";
+    if (!(p->delta_t > 0) || p->delta_t > 0.5 * p->dx * (1 + 1e-12))
+        return "delta_t must satisfy 0 < delta_t <= dx/2 (surrounding points inside the two cells)";
+    if (!(p->dt > 0)) return "dt must be > 0";
+    if (p->lattice_hg != 5 && p->lattice_hg != 9) return "lattice_hg must be 5 or 9";
+    if (p->precision != EULBFS_FP64 && p->precision != EULBFS_FP32) return "unknown precision";
+    if (p->kernel != EULBFS_KERNEL_FUSED && p->kernel != EULBFS_KERNEL_SPLIT) return "unknown kernel variant";
+    if (p->surf_model != 0 && p->surf_model != 1) return "surf_model must be 0 or 1";
+    for (int k = 0; k < 3; ++k) {
+        if (!(p->rho[k] > 0)) return "densities must be > 0";
+        if (!(p->mu[k] >= 0) || !(p->lambda[k] >= 0)) return "viscosities and conductivities must be >= 0";
+        if (!(p->cp[k] > 0)) return "heat capacities must be > 0";
+    }
+    if (!(p->latent >= 0)) return "latent heat must be >= 0";
+    if (!(p->T_l >= p->T_s)) return "T_l must be >= T_s";
+    if (!(p->sigma >= 0)) return "sigma must be >= 0";
+    if (!(p->xi > 0)) return "xi must be > 0";
+    if (!(p->mobility >= 0) || !(p->Qg > 0)) return "mobility must be >= 0 and Qg > 0";
+    for (int a = 0; a < 2; ++a) {
+        const eulbfs_bc& lo = p->bc[2 * a];
+        const eulbfs_bc& hi = p->bc[2 * a + 1];
+        if ((lo.periodic != 0) != (hi.periodic != 0)) return "periodic must agree on opposite sides";
+    }
+    for (int s = 0; s < 4; ++s) {
+        const eulbfs_bc& b = p->bc[s];
+        if (b.periodic) continue;
+        if (b.flow < 0 || b.flow > 2) return "unknown flow boundary rule";
+        if (b.heat < 0 || b.heat > 1) return "unknown heat boundary rule";
+        if (!(b.theta_deg > 0 && b.theta_deg < 180)) return "contact angle must be in (0, 180) deg";
+    }
+    const int tiles[][2] = {{0, 0}, {32, 8}, {64, 4}, {16, 16}, {64, 8}};
+    bool ok = false;
+    for (auto& t : tiles) ok |= (p->tile_x == t[0] && p->tile_y == t[1]);
+    if (!ok) return "tile must be 0x0, 32x8, 64x4, 16x16 or 64x8";
+    return "";
+}
+
+int tile_of(const eulbfs_params* p)
+{
+    if (p->tile_x == 64 && p->tile_y == 4) return TILE_64x4;
+    if (p->tile_x == 16 && p->tile_y == 16) return TILE_16x16;
+    if (p->tile_x == 64 && p->tile_y == 8) return TILE_64x8;
+    return TILE_32x8;
+}
+
+DevParams make_dev(const eulbfs_params* p)
+{
+    DevParams d;
+    std::memset(&d, 0, sizeof d);
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.pitch = round_pitch(p->nx);
+    d.lattice_hg = p->lattice_hg;
+    d.surf_model = p->surf_model;
+    d.periodic_x = p->bc[0].periodic ? 1 : 0;
+    d.periodic_y = p->bc[2].periodic ? 1 : 0;
+    for (int s = 0; s < 4; ++s) {
+        d.flow[s] = p->bc[s].flow;
+        d.heat[s] = p->bc[s].heat;
+        d.T_w[s] = p->bc[s].T_w;
+        d.wet[s] = p->dx * (4.0 / p->xi) * std::cos(p->bc[s].theta_deg * M_PI / 180.0);
+    }
+    d.dx = p->dx;
+    d.inv_2dx = 1.0 / (2.0 * p->dx);
+    d.inv_dx2 = 1.0 / (p->dx * p->dx);
+    d.delta_t = p->delta_t;
+    d.dt = p->dt;
+    d.inv_dt = 1.0 / p->dt;
+    for (int k = 0; k < 3; ++k) {
+        d.rho[k] = p->rho[k];
+        d.mu[k] = p->mu[k];
+        d.lam[k] = p->lambda[k];
+        d.cp[k] = p->cp[k];
+    }
+    d.latent = p->latent;
+    d.T_s = p->T_s;
+    d.T_l = p->T_l;
+    d.beta = 12.0 * p->sigma / p->xi;
+    d.kappa = 1.5 * p->xi * p->sigma;
+    d.a_g = p->mobility / (p->Qg * p->delta_t);
+    d.muQ = p->Qg;
+    d.cpref = 0.5 * (p->cp[0] + p->cp[1]);
+    d.k_h = 3.0 / (d.cpref * p->delta_t);
+    d.k_f = 3.0 / p->delta_t;
+    d.gx = p->gx;
+    d.gy = p->gy;
+    d.expansion = 1.0 - p->rho[0] / p->rho[1];
+    return d;
+}
+
+// Byte offsets of every region of a solver's workspace.
+struct Layout {
+    size_t state_bytes;  // one copy of W
+    size_t plane_R, plane_H;
+    size_t W0, fsdot, WA, WB, staging, staging_bytes, red_partial, red_out;
+    int red_blocks;
+    bool split;
+    size_t g, prim, Fx, Fy;  // split scratch
+    int gpitch, fpitch;
+    size_t gplane_H, gplane_R, pstride, fstride;
+    size_t total;
+};
+
+Layout make_layout(const eulbfs_params* p)
+{
+    Layout L{};
+    const size_t rs = p->precision == EULBFS_FP32 ? 4 : 8;
+    const int pitch = round_pitch(p->nx);
+    L.plane_H = align_up((size_t)p->ny * pitch * 8);
+    L.plane_R = align_up((size_t)p->ny * pitch * rs);
+    L.state_bytes = L.plane_H + 4 * L.plane_R;
+    size_t off = 0;
+    L.W0 = off;
+    off += L.state_bytes;
+    L.fsdot = off;
+    off += L.plane_R;
+    // WA and WB are dead between steps: the same bytes stage dense double
+    // planes for initialisation, checkpoints and queries.
+    const size_t gn = (size_t)(p->nx + 2 * NG) * (p->ny + 2 * NG);
+    L.staging_bytes = align_up(std::max((size_t)6 * p->nx * p->ny, 5 * gn) * 8);
+    L.staging = off;
+    L.WA = off;
+    L.WB = off + L.state_bytes;
+    off += std::max(2 * L.state_bytes, L.staging_bytes);
+    const size_t ncell = (size_t)p->nx * p->ny;
+    L.red_blocks = (int)std::min<size_t>(1024, (ncell + 255) / 256);
+    L.red_partial = off;
+    off += align_up((size_t)L.red_blocks * NRED * 8);
+    L.red_out = off;
+    off += align_up(16 * 8);
+    L.split = p->kernel == EULBFS_KERNEL_SPLIT;
+    L.gpitch = round_pitch(p->nx + 2 * NG);
+    L.fpitch = round_pitch(p->nx + 1);
+    L.gplane_H = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * 8);
+    L.gplane_R = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * rs);
+    L.pstride = L.gplane_R / rs;
+    L.fstride = align_up((size_t)(p->ny + 1) * L.fpitch * rs) / rs;
+    if (L.split) {
+        L.g = off;
+        off += L.gplane_H + 4 * L.gplane_R;
+        L.prim = off;
+        off += (NPRIM + 1) * L.gplane_R;
+        L.Fx = off;
+        off += 5 * L.fstride * rs;
+        L.Fy = off;
+        off += 5 * L.fstride * rs;
+    }
+    L.total = off;
+    return L;
+}
+
+size_t split_scratch_bytes(const Layout& L, size_t rs)
+{
+    return L.gplane_H + 4 * L.gplane_R + (NPRIM + 1) * L.gplane_R + 10 * L.fstride * rs;
+}
+
+template <typename R>
+State<R> state_at(char* base, size_t off, const Layout& L)
+{
+    State<R> s;
+    s.H = (double*)(base + off);
+    s.p = (R*)(base + off + L.plane_H);
+    s.mx = (R*)(base + off + L.plane_H + L.plane_R);
+    s.my = (R*)(base + off + L.plane_H + 2 * L.plane_R);
+    s.C = (R*)(base + off + L.plane_H + 3 * L.plane_R);
+    return s;
+}
+
+template <typename R>
+SplitScratch<R> split_at(char* base, const Layout& L)
+{
+    SplitScratch<R> X;
+    X.g.H = (double*)(base + L.g);
+    X.g.p = (R*)(base + L.g + L.gplane_H);
+    X.g.mx = (R*)(base + L.g + L.gplane_H + L.gplane_R);
+    X.g.my = (R*)(base + L.g + L.gplane_H + 2 * L.gplane_R);
+    X.g.C = (R*)(base + L.g + L.gplane_H + 3 * L.gplane_R);
+    X.gpitch = L.gpitch;
+    X.prim = (R*)(base + L.prim);
+    X.pstride = L.pstride;
+    X.Fx = (R*)(base + L.Fx);
+    X.Fy = (R*)(base + L.Fy);
+    X.fpitch = L.fpitch;
+    X.fstride = L.fstride;
+    return X;
+}
+
+template <typename R>
+__global__ void k_to_double(const R* src, size_t spitch, int w, int h, double* dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i < w && j < h) dst[(size_t)j * w + i] = (double)src[(size_t)j * spitch + i];
+}
+
+template <typename R>
+hipError_t to_double(const R* src, size_t spitch, int w, int h, double* dst, hipStream_t st)
+{
+    const dim3 b(64, 4), g((w + 63) / 64, (h + 3) / 4);
+    hipLaunchKernelGGL(k_to_double<R>, g, b, 0, st, src, spitch, w, h, dst);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+struct eulbfs_solver {
+    eulbfs_params prm;
+    DevParams dp;
+    Layout L;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    bool own_ws = false;
+    int tile = TILE_32x8;
+    int64_t steps = 0;
+    bool poisoned = false;
+    std::string err;
+};
+
+namespace {
+
+template <typename R>
+int enqueue_steps(eulbfs_solver* h, int64_t n)
+{
+    std::string* err = &h->err;
+    const DevParams& P = h->dp;
+    const Layout& L = h->L;
+    State<R> W0 = state_at<R>(h->ws, L.W0, L), WA = state_at<R>(h->ws, L.WA, L), WB = state_at<R>(h->ws, L.WB, L);
+    R* fsdot = (R*)(h->ws + L.fsdot);
+    const StageCoef K1{0.0, 1.0, 1.0, 0}, K2{0.75, 0.25, 0.25, 0}, K3{1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 1};
+    for (int64_t s = 0; s < n; ++s) {
+        if (h->prm.kernel == EULBFS_KERNEL_SPLIT) {
+            const SplitScratch<R> X = split_at<R>(h->ws, L);
+            HIP_TRY(launch_stage_split<R>(P, X, K1, W0, W0, WA, fsdot, nullptr, 0, h->stream));
+            HIP_TRY(launch_stage_split<R>(P, X, K2, WA, W0, WB, fsdot, nullptr, 0, h->stream));
+            HIP_TRY(launch_stage_split<R>(P, X, K3, WB, W0, W0, fsdot, nullptr, 0, h->stream));
+        } else {
+            HIP_TRY(launch_stage_fused<R>(P, h->tile, K1, W0, W0, WA, fsdot, h->stream));
+            HIP_TRY(launch_stage_fused<R>(P, h->tile, K2, WA, W0, WB, fsdot, h->stream));
+            HIP_TRY(launch_stage_fused<R>(P, h->tile, K3, WB, W0, W0, fsdot, h->stream));
+        }
+    }
+    h->steps += n;
+    return EULBFS_OK;
+}
+
+template <typename R>
+int do_init(eulbfs_solver* h, const eulbfs_init* init)
+{
+    std::string* err = &h->err;
+    const Layout& L = h->L;
+    const size_t n6 = (size_t)6 * h->prm.nx * h->prm.ny;
+    double* stage = (double*)(h->ws + L.staging);
+    const double* src = init->planes;
+    if (!init->on_device) {
+        HIP_TRY(hipMemcpyAsync(stage, init->planes, n6 * 8, hipMemcpyHostToDevice, h->stream));
+        src = stage;
+    }
+    State<R> W0 = state_at<R>(h->ws, L.W0, L);
+    R* fsdot = (R*)(h->ws + L.fsdot);
+    if (init->kind == EULBFS_INIT_PRIMITIVE)
+        HIP_TRY(launch_init<R>(h->dp, src, W0, fsdot, h->stream));
+    else
+        HIP_TRY(launch_set_conserved<R>(h->dp, src, W0, fsdot, -1, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return EULBFS_OK;
+}
+
+template <typename R>
+int do_diag(eulbfs_solver* h, double* host_out)
+{
+    std::string* err = &h->err;
+    const Layout& L = h->L;
+    State<R> W0 = state_at<R>(h->ws, L.W0, L);
+    double* part = (double*)(h->ws + L.red_partial);
+    double* dout = (double*)(h->ws + L.red_out);
+    HIP_TRY(launch_reduce<R>(h->dp, W0, part, L.red_blocks, dout, h->stream));
+    double r[NRED];
+    HIP_TRY(hipMemcpyAsync(r, dout, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double dV = h->prm.dx * h->prm.dx;
+    host_out[0] = r[0] * dV;
+    host_out[1] = r[1] * dV;
+    host_out[2] = r[2] * dV;
+    host_out[3] = r[3] * dV;
+    host_out[4] = r[4];
+    host_out[5] = r[5];
+    host_out[6] = r[6] * h->prm.dx;
+    host_out[7] = (double)h->steps * h->prm.dt;
+    host_out[8] = (double)h->steps;
+    host_out[9] = h->prm.dt;
+    return EULBFS_OK;
+}
+
+template <typename R>
+int do_query_field(eulbfs_solver* h, int what, void* out, size_t bytes, int on_dev)
+{
+    std::string* err = &h->err;
+    const Layout& L = h->L;
+    const int nx = h->prm.nx, ny = h->prm.ny;
+    const size_t n = (size_t)nx * ny;
+    const size_t gn = (size_t)(nx + 2 * NG) * (ny + 2 * NG);
+    size_t need = what == EULBFS_FIELD_W_ALL ? 6 * n * 8 : (what == EULBFS_FIELD_W_GHOSTED ? 5 * gn * 8 : n * 8);
+    if (bytes < need) return set_err(err, EULBFS_EINVAL, "output buffer too small");
+    State<R> W0 = state_at<R>(h->ws, L.W0, L);
+    const R* fsdot = (const R*)(h->ws + L.fsdot);
+    double* stage = (double*)(h->ws + L.staging);
+    if (what == EULBFS_FIELD_W_ALL) {
+        for (int k = 0; k < 6; ++k) HIP_TRY(launch_export<R>(h->dp, W0, fsdot, k, stage + k * n, h->stream));
+    } else {
+        HIP_TRY(launch_export<R>(h->dp, W0, fsdot, what, stage, h->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(out, stage, need, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return EULBFS_OK;
+}
+
+template <typename R>
+int do_set_field(eulbfs_solver* h, int what, const void* in, size_t bytes, int on_dev)
+{
+    std::string* err = &h->err;
+    const Layout& L = h->L;
+    const size_t n = (size_t)h->prm.nx * h->prm.ny;
+    const size_t need = what == EULBFS_FIELD_W_ALL ? 6 * n * 8 : n * 8;
+    if (bytes < need) return set_err(err, EULBFS_EINVAL, "input buffer too small");
+    double* stage = (double*)(h->ws + L.staging);
+    HIP_TRY(hipMemcpyAsync(stage, in, need, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+    State<R> W0 = state_at<R>(h->ws, L.W0, L);
+    R* fsdot = (R*)(h->ws + L.fsdot);
+    HIP_TRY(launch_set_conserved<R>(h->dp, stage, W0, fsdot, what == EULBFS_FIELD_W_ALL ? -1 : what, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->poisoned = false;
+    return EULBFS_OK;
+}
+
+template <typename R>
+int do_residual(eulbfs_solver* h, double* Rout, double* Fx, double* Fy, int on_dev)
+{
+    std::string* err = &h->err;
+    const Layout& L = h->L;
+    const int nx = h->prm.nx, ny = h->prm.ny;
+    const size_t rs = sizeof(R);
+    // split scratch (unless the workspace holds one), residual planes in the
+    // state's pitch layout, dense double staging for the copies out
+    const size_t sb = L.split ? 0 : align_up(split_scratch_bytes(L, rs));
+    const size_t rbytes = 5 * L.plane_R;
+    const size_t dense = align_up((size_t)5 * (nx + 1) * (ny + 1) * 8);
+    char* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, sb + rbytes + dense));
+    SplitScratch<R> X;
+    if (L.split) {
+        X = split_at<R>(h->ws, L);
+    } else {
+        Layout L2 = L;
+        L2.g = 0;
+        L2.prim = L2.g + L.gplane_H + 4 * L.gplane_R;
+        L2.Fx = L2.prim + (NPRIM + 1) * L.gplane_R;
+        L2.Fy = L2.Fx + 5 * L.fstride * rs;
+        X = split_at<R>(tmp, L2);
+    }
+    R* res = (R*)(tmp + sb);
+    double* dd = (double*)(tmp + sb + rbytes);
+    State<R> W0 = state_at<R>(h->ws, L.W0, L);
+    R* fsdot = (R*)(h->ws + L.fsdot);
+    const StageCoef K{0.0, 1.0, 1.0, 0};
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t rstride = L.plane_R / rs;
+    hipError_t e = launch_stage_split<R>(h->dp, X, K, W0, W0, W0, fsdot, res, rstride, h->stream);
+    if (e == hipSuccess && Rout) {
+        for (int k = 0; k < 5 && e == hipSuccess; ++k)
+            e = to_double<R>(res + k * rstride, h->dp.pitch, nx, ny, dd + (size_t)k * nx * ny, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(Rout, dd, (size_t)5 * nx * ny * 8, kind, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (e == hipSuccess && Fx) {
+        for (int k = 0; k < 5 && e == hipSuccess; ++k)
+            e = to_double<R>(X.Fx + k * X.fstride, X.fpitch, nx + 1, ny, dd + (size_t)k * (nx + 1) * ny, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(Fx, dd, (size_t)5 * (nx + 1) * ny * 8, kind, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (e == hipSuccess && Fy) {
+        for (int k = 0; k < 5 && e == hipSuccess; ++k)
+            e = to_double<R>(X.Fy + k * X.fstride, X.fpitch, nx, ny + 1, dd + (size_t)k * nx * (ny + 1), h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(Fy, dd, (size_t)5 * nx * (ny + 1) * 8, kind, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    const hipError_t ef = hipFree(tmp);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return set_err(err, EULBFS_EDEVICE, std::string("residual: ") + hipGetErrorString(e));
+    return EULBFS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int eulbfs_check_params(const eulbfs_params* prm, char* msg, size_t msg_len)
+{
+    const std::string e = check(prm);
+    if (msg && msg_len) {
+        std::snprintf(msg, msg_len, "%s", e.c_str());
+    }
+    if (!e.empty()) return set_err(nullptr, EULBFS_EINVAL, e);
+    return EULBFS_OK;
+}
+
+size_t eulbfs_workspace_bytes(const eulbfs_params* prm)
+{
+    if (!check(prm).empty()) return 0;
+    return make_layout(prm).total;
+}
+
+int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes, void* hip_stream,
+                  eulbfs_solver** out)
+{
+    std::string* err = nullptr;
+    if (!out) return set_err(err, EULBFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    const std::string e = check(prm);
+    if (!e.empty()) return set_err(err, EULBFS_EINVAL, e);
+    if (!init || !init->planes) return set_err(err, EULBFS_EINVAL, "init or init->planes is NULL");
+    if (init->kind != EULBFS_INIT_PRIMITIVE && init->kind != EULBFS_INIT_CONSERVED)
+        return set_err(err, EULBFS_EINVAL, "unknown init kind");
+    const Layout L = make_layout(prm);
+    if (d_ws && ws_bytes < L.total) return set_err(err, EULBFS_ENOMEM, "workspace smaller than eulbfs_workspace_bytes()");
+    if (d_ws && ((uintptr_t)d_ws % ALIGN) != 0) return set_err(err, EULBFS_EINVAL, "workspace must be 256-byte aligned");
+    eulbfs_solver* h = new eulbfs_solver();
+    h->prm = *prm;
+    h->dp = make_dev(prm);
+    h->L = L;
+    h->stream = (hipStream_t)hip_stream;
+    h->tile = tile_of(prm);
+    if (d_ws) {
+        h->ws = (char*)d_ws;
+    } else {
+        hipError_t he = hipMalloc(&h->ws, L.total);
+        if (he != hipSuccess) {
+            delete h;
+            return set_err(err, EULBFS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(he));
+        }
+        h->own_ws = true;
+    }
+    int rc = prm->precision == EULBFS_FP32 ? do_init<float>(h, init) : do_init<double>(h, init);
+    if (rc != EULBFS_OK) {
+        g_thread_err = h->err;
+        eulbfs_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return EULBFS_OK;
+}
+
+int eulbfs_step(eulbfs_t h, int64_t nsteps)
+{
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    if (nsteps < 0) return set_err(&h->err, EULBFS_EINVAL, "nsteps must be >= 0");
+    if (h->poisoned) return set_err(&h->err, EULBFS_EUNSTABLE, "state is non-finite; restore a checkpoint");
+    return h->prm.precision == EULBFS_FP32 ? enqueue_steps<float>(h, nsteps) : enqueue_steps<double>(h, nsteps);
+}
+
+int eulbfs_run(eulbfs_t h, int64_t nsteps)
+{
+    int rc = eulbfs_step(h, nsteps);
+    if (rc != EULBFS_OK) return rc;
+    double d[EULBFS_NDIAG];
+    rc = h->prm.precision == EULBFS_FP32 ? do_diag<float>(h, d) : do_diag<double>(h, d);
+    if (rc != EULBFS_OK) return rc;
+    if (d[5] != 0.0 || !std::isfinite(d[0]) || !std::isfinite(d[2])) {
+        h->poisoned = true;
+        return set_err(&h->err, EULBFS_EUNSTABLE, "non-finite values in the state after step " + std::to_string(h->steps));
+    }
+    return EULBFS_OK;
+}
+
+int eulbfs_query(eulbfs_t h, int32_t what, void* out, size_t bytes, int32_t out_on_device)
+{
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    if (!out) return set_err(&h->err, EULBFS_EINVAL, "out is NULL");
+    if (what == EULBFS_SCALAR_DIAG) {
+        if (bytes < EULBFS_NDIAG * sizeof(double)) return set_err(&h->err, EULBFS_EINVAL, "output buffer too small");
+        double d[EULBFS_NDIAG];
+        int rc = h->prm.precision == EULBFS_FP32 ? do_diag<float>(h, d) : do_diag<double>(h, d);
+        if (rc != EULBFS_OK) return rc;
+        if (out_on_device) {
+            hipError_t e = hipMemcpy(out, d, sizeof d, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return set_err(&h->err, EULBFS_EDEVICE, hipGetErrorString(e));
+        } else {
+            std::memcpy(out, d, sizeof d);
+        }
+        return EULBFS_OK;
+    }
+    if (what < 0 || what > EULBFS_FIELD_W_GHOSTED) return set_err(&h->err, EULBFS_EINVAL, "unknown selector");
+    return h->prm.precision == EULBFS_FP32 ? do_query_field<float>(h, what, out, bytes, out_on_device)
+                                           : do_query_field<double>(h, what, out, bytes, out_on_device);
+}
+
+int eulbfs_set_field(eulbfs_t h, int32_t what, const void* in, size_t bytes, int32_t in_on_device)
+{
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    if (!in) return set_err(&h->err, EULBFS_EINVAL, "in is NULL");
+    if (!(what >= EULBFS_FIELD_H && what <= EULBFS_FIELD_FSDOT) && what != EULBFS_FIELD_W_ALL)
+        return set_err(&h->err, EULBFS_EINVAL, "only conserved planes, dF_s/dt or W_ALL can be set");
+    return h->prm.precision == EULBFS_FP32 ? do_set_field<float>(h, what, in, bytes, in_on_device)
+                                           : do_set_field<double>(h, what, in, bytes, in_on_device);
+}
+
+int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device)
+{
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    return h->prm.precision == EULBFS_FP32 ? do_residual<float>(h, R, Fx, Fy, on_device)
+                                           : do_residual<double>(h, R, Fx, Fy, on_device);
+}
+
+int eulbfs_destroy(eulbfs_t h)
+{
+    if (!h) return EULBFS_OK;
+    if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+    return EULBFS_OK;
+}
+
+const char* eulbfs_last_error(eulbfs_t h)
+{
+    if (!h) return g_thread_err.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,391 @@
+// Device-side building blocks of the EULBFS time step for gfx950.
+//
+// Everything here is templated on the field/arithmetic type R (double or
+// float).  The total enthalpy H is always stored and combined in double, and
+// the closure H -> (T, F_l) of Eqs. (5)-(6) always runs in double: in FP32
+// mode the enthalpy increments per step are far below the float spacing of
+// H ~ L near the melting point.
+//
+// Storage: structure of arrays.  Each conserved field is one plane of
+// ny rows of `pitch` elements (pitch >= nx, a multiple of 64), x fastest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eulbfs {
+
+constexpr int NG = 3;  // ghost layers needed by the stencil (C -> mu_c -> grad -> face)
+
+enum { FLOW_NOSLIP = 0, FLOW_FREESLIP = 1, FLOW_OUTLET = 2 };
+enum { HEAT_ADIABATIC = 0, HEAT_DIRICHLET = 1 };
+
+// Constants of one problem, derived on the host once (passed by value as a
+// kernel argument).
+struct DevParams {
+    int nx, ny, pitch;
+    int lattice_hg;   // 9 or 5 (h and g); the flow lattice is always D2Q9
+    int surf_model;   // 0: -C grad mu_c, 1: -F_l C grad mu_c
+    int periodic_x, periodic_y;
+    int flow[4], heat[4];
+    double dx, inv_2dx, inv_dx2, delta_t, dt;
+    double rho[3], mu[3], lam[3], cp[3];  // solid, liquid, gas (Eq. 7)
+    double latent, T_s, T_l;
+    double beta, kappa;  // 12 sigma/xi, 3 xi sigma/2 (Sec. 2.3.1)
+    double a_g;          // tau_g - 1/2 = M_c / (Q_g delta_t)   (Eq. 41)
+    double muQ;          // Q_g
+    double cpref;        // (C_p,s + C_p,l)/2                   (Sec. 2.1.2)
+    double k_h;          // 3 / (C_p,ref delta_t): tau_h - 1/2 = k_h lambda/rho
+    double k_f;          // 3 / delta_t:           tau_f - 1/2 = k_f mu/rho
+    double gx, gy;
+    double expansion;    // 1 - rho_s/rho_l
+    double T_w[4];
+    double wet[4];       // dx (4/xi) cos(theta): ghost C offset per mirror distance
+    double inv_dt;
+};
+
+// Pointers to one copy of the conserved vector W = (H, p, Mx, My, C).
+template <typename R>
+struct State {
+    double* H;
+    R* p;
+    R* mx;
+    R* my;
+    R* C;
+};
+
+template <typename R>
+struct Cons {
+    double H;
+    R p, mx, my, C;
+};
+
+__device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+__device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// Eq. (7): gamma = F_s g_s + (1 - F_s) C g_l + (1 - F_s)(1 - C) g_g.
+template <typename R>
+__device__ __forceinline__ R mix(const double g[3], R C, R Fs)
+{
+    const R gs = R(g[0]), gl = R(g[1]), gg = R(g[2]);
+    const R cond = gg + C * (gl - gg);  // C g_l + (1 - C) g_g
+    return cond + Fs * (gs - cond);
+}
+
+// Eqs. (5)-(6) with H = C_p T + L F_l and the condensed-phase mixtures
+// C_p^S = Eq.7(C, F_s = C), C_p^L = Eq.7(C, F_s = 0).  Cc is C clamped to [0,1].
+__device__ __forceinline__ void closure(const DevParams& P, double H, double Cc, double& Fl, double& T)
+{
+    const double cpS = mix<double>(P.cp, Cc, Cc);
+    const double cpL = mix<double>(P.cp, Cc, 0.0);
+    const double Hs = cpS * P.T_s;
+    const double Hl = cpL * P.T_l + P.latent;
+    if (H < Hs) {
+        Fl = 0.0;
+        T = P.T_s + (H - Hs) / cpS;
+    } else if (H > Hl) {
+        Fl = 1.0;
+        T = P.T_l + (H - Hl) / cpL;
+    } else {
+        const double d = Hl - Hs;
+        Fl = d > 1e-300 ? (H - Hs) / d : 1.0;
+        T = P.T_s + Fl * (P.T_l - P.T_s);
+    }
+}
+
+__device__ __forceinline__ double solid_fraction(const DevParams& P, double H, double C)
+{
+    const double Cc = clamp01(C);
+    double Fl, T;
+    closure(P, H, Cc, Fl, T);
+    return Cc * (1.0 - Fl);
+}
+
+// Enthalpy of a state with temperature T and liquid fraction Fl.
+__device__ __forceinline__ double enthalpy_of(const DevParams& P, double T, double Fl, double C)
+{
+    const double Cc = clamp01(C);
+    const double cpS = mix<double>(P.cp, Cc, Cc);
+    const double cpL = mix<double>(P.cp, Cc, 0.0);
+    const double Hs = cpS * P.T_s;
+    const double Hl = cpL * P.T_l + P.latent;
+    return (1.0 - Fl) * (Hs + cpS * (T - P.T_s)) + Fl * (Hl + cpL * (T - P.T_l));
+}
+
+// Inverse closure for a Dirichlet ghost cell: phase from T against T_s, T_l.
+__device__ __forceinline__ double ghost_enthalpy(const DevParams& P, double T, double C)
+{
+    double Fl;
+    if (T > P.T_l)
+        Fl = 1.0;
+    else if (T < P.T_s)
+        Fl = 0.0;
+    else if (P.T_l > P.T_s)
+        Fl = (T - P.T_s) / (P.T_l - P.T_s);
+    else
+        Fl = 1.0;
+    return enthalpy_of(P, T, Fl, C);
+}
+
+template <typename R>
+__device__ __forceinline__ Cons<R> read_cell(const State<R>& S, int pitch, int i, int j)
+{
+    const size_t q = (size_t)j * pitch + i;
+    Cons<R> w;
+    w.H = S.H[q];
+    w.p = S.p[q];
+    w.mx = S.mx[q];
+    w.my = S.my[q];
+    w.C = S.C[q];
+    return w;
+}
+
+// Wall rule for ghost layer k (1..3) of `side` (0 x-, 1 x+, 2 y-, 3 y+):
+// m is the mirrored interior cell, Cw the C of the first interior cell.
+template <typename R>
+__device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int k, const Cons<R>& m, R Cw)
+{
+    Cons<R> g;
+    g.p = m.p;
+    const bool xside = side < 2;
+    const R mn = xside ? m.mx : m.my;
+    const R mt = xside ? m.my : m.mx;
+    const int f = P.flow[side];
+    const R gn = f == FLOW_OUTLET ? mn : -mn;
+    const R gt = f == FLOW_NOSLIP ? -mt : mt;
+    g.mx = xside ? gn : gt;
+    g.my = xside ? gt : gn;
+    g.C = m.C + R((2 * k - 1) * P.wet[side]) * Cw * (R(1) - Cw);
+    if (P.heat[side] == HEAT_DIRICHLET) {
+        double Fl, Tm;
+        closure(P, m.H, clamp01((double)m.C), Fl, Tm);
+        const double Tg = 2.0 * P.T_w[side] - Tm;
+        g.H = ghost_enthalpy(P, Tg, (double)g.C);
+    } else {
+        g.H = m.H;
+    }
+    return g;
+}
+
+__device__ __forceinline__ int wrap(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Conserved state at (i, j) for j inside [0, ny): interior read, periodic copy
+// or x-wall rule.
+template <typename R>
+__device__ __forceinline__ Cons<R> load_x(const DevParams& P, const State<R>& S, int i, int j)
+{
+    if (i >= 0 && i < P.nx) return read_cell(S, P.pitch, i, j);
+    if (P.periodic_x) return read_cell(S, P.pitch, wrap(i, P.nx), j);
+    int side, k, m, first;
+    if (i < 0) {
+        side = 0; k = -i; m = k - 1; first = 0;
+    } else {
+        side = 1; k = i - P.nx + 1; m = P.nx - k; first = P.nx - 1;
+    }
+    const Cons<R> wm = read_cell(S, P.pitch, m, j);
+    const R Cw = S.C[(size_t)j * P.pitch + first];
+    return wall_ghost(P, side, k, wm, Cw);
+}
+
+// Conserved state at any (i, j) of the grid extended by the three-layer
+// ghost ring: x rule on the interior rows, then the y rule on every column
+// (corner cells take the y rule of x-ghost cells).  Indices beyond the ring
+// are clamped onto it (only partial edge tiles reach them; their results are
+// never stored).
+template <typename R>
+__device__ __forceinline__ Cons<R> load_bc(const DevParams& P, const State<R>& S, int i, int j)
+{
+    i = min(max(i, -NG), P.nx + NG - 1);
+    j = min(max(j, -NG), P.ny + NG - 1);
+    if (j >= 0 && j < P.ny) return load_x(P, S, i, j);
+    if (P.periodic_y) return load_x(P, S, i, wrap(j, P.ny));
+    int side, k, m, first;
+    if (j < 0) {
+        side = 2; k = -j; m = k - 1; first = 0;
+    } else {
+        side = 3; k = j - P.ny + 1; m = P.ny - k; first = P.ny - 1;
+    }
+    const Cons<R> wm = load_x(P, S, i, m);
+    const R Cw = load_x(P, S, i, first).C;
+    return wall_ghost(P, side, k, wm, Cw);
+}
+
+// Primitive record of one cell used by the face fluxes.
+enum { VT = 0, VC, VFS, VU, VV, VP, VMU, NPRIM };  // + rho stored after
+
+// Closure, Eq. (7) density and velocity of one cell (mu_c done separately).
+template <typename R>
+__device__ __forceinline__ void primitives(const DevParams& P, const Cons<R>& w, R out[NPRIM + 1])
+{
+    const double Cc = clamp01((double)w.C);
+    double Fl, T;
+    closure(P, w.H, Cc, Fl, T);
+    const R Fs = R(Cc * (1.0 - Fl));
+    const R rho = mix<R>(P.rho, R(Cc), Fs);
+    const R inv = R(3) / rho;  // 1 / (rho c_s^2)
+    out[VT] = R(T);
+    out[VC] = w.C;
+    out[VFS] = Fs;
+    out[VU] = w.mx * inv;
+    out[VV] = w.my * inv;
+    out[VP] = w.p;
+    out[VMU] = R(0);
+    out[NPRIM] = rho;
+}
+
+// Chemical potential (Sec. 2.3.1): 2 beta C (C-1)(2C-1) - kappa lap C.
+template <typename R>
+__device__ __forceinline__ R chem_potential(const DevParams& P, R C, R cE, R cW, R cN, R cS)
+{
+    const R lap = (cE + cW + cN + cS - R(4) * C) * R(P.inv_dx2);
+    return R(2 * P.beta) * C * (C - R(1)) * (R(2) * C - R(1)) - R(P.kappa) * lap;
+}
+
+// ---------------------------------------------------------------------------
+// Face flux (Eqs. 53-56 with Eqs. 9, 13, 16, 29, 33, 35, 37, 42, 44, 46).
+//
+// Local frame: n is the face normal (from cell a to cell b), t the tangent.
+// The D2Q9 set maps onto itself under the x <-> y reflection, so one routine
+// serves both orientations: it takes velocities (u_n, u_t) and gradients
+// (d/dn, d/dt) and returns (F_H, F_p, F_Mn, F_Mt, F_C) with F_Mn = sum e_n e_n f*,
+// F_Mt = sum e_n e_t f*.
+//
+// Surrounding points x_f - e delta_t (Eq. 54): e_n > 0 lies in cell a,
+// e_n < 0 in cell b, e_n = 0 on the face (average of both extrapolations).
+// With a_X = tau_X - 1/2 the star distribution is
+//   X* = (1 - a_X) X^eq(x_f) + a_X X^eq(x_f - e delta_t)
+// so each flux is (1 - a_X) times a moment of the face equilibrium (known in
+// closed form from Eqs. 11, 29, 42) plus a_X times the same moment of the
+// point equilibria.
+// ---------------------------------------------------------------------------
+template <typename R, int LAT>
+__device__ __forceinline__ void face_flux(const DevParams& P, const R va[NPRIM], const R gna[NPRIM],
+                                          const R gta[NPRIM], const R vb[NPRIM], const R gnb[NPRIM],
+                                          const R gtb[NPRIM], R F[5])
+{
+    const R h = R(0.5 * P.dx);
+    const R ds = R(P.delta_t);
+    const R sh = R(0.5 * P.dx - P.delta_t);
+    R A[NPRIM], B[NPRIM], M[NPRIM], da[NPRIM], db[NPRIM], dm[NPRIM];
+#pragma unroll
+    for (int k = 0; k < NPRIM; ++k) {
+        A[k] = va[k] + sh * gna[k];
+        B[k] = vb[k] - sh * gnb[k];
+        M[k] = R(0.5) * ((va[k] + h * gna[k]) + (vb[k] - h * gnb[k]));
+        da[k] = ds * gta[k];
+        db[k] = ds * gtb[k];
+        dm[k] = R(0.5) * (da[k] + db[k]);
+    }
+    // old-level face state (text after Eq. 54) -> Eq. (7)
+    const R Cf = clamp01(M[VC]);
+    const R Fsf = clamp01(M[VFS]);
+    const R rho_f = mix<R>(P.rho, Cf, Fsf);
+    const R mu_f = mix<R>(P.mu, Cf, Fsf);
+    const R lam_f = mix<R>(P.lam, Cf, Fsf);
+    const R cp_f = mix<R>(P.cp, Cf, Fsf);
+    const R cpref = R(P.cpref);
+    const R Q = R(P.muQ);
+
+    R p_f = 0, m_n = 0, m_t = 0, C_new = 0, SH = 0, SG = 0, SMn = 0, SMt = 0;
+#pragma unroll
+    for (int pn = 0; pn < 3; ++pn) {
+        const int en = pn == 0 ? 1 : (pn == 1 ? -1 : 0);
+        const R* base = pn == 0 ? A : (pn == 1 ? B : M);
+        const R* dd = pn == 0 ? da : (pn == 1 ? db : dm);
+#pragma unroll
+        for (int pt = 0; pt < 3; ++pt) {
+            const int et = pt == 0 ? 0 : (pt == 1 ? 1 : -1);
+            const R w9 = en == 0 ? (et == 0 ? R(4.0 / 9.0) : R(1.0 / 9.0)) : (et == 0 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+            const bool in_hg = LAT == 9 || en == 0 || et == 0;
+            const R wh = LAT == 9 ? w9 : (en == 0 && et == 0 ? R(1.0 / 3.0) : R(1.0 / 6.0));
+            // point values (Eq. 54): base - e_t * delta_t * d/dt
+            const R C = base[VC] - R(et) * dd[VC];
+            const R Fs = base[VFS] - R(et) * dd[VFS];
+            const R un = base[VU] - R(et) * dd[VU];
+            const R ut = base[VV] - R(et) * dd[VV];
+            const R p = base[VP] - R(et) * dd[VP];
+            const R Cc = clamp01(C);
+            const R Fsc = clamp01(Fs);
+            const R rho_pt = mix<R>(P.rho, Cc, Fsc);
+            const R eu = R(en) * un + R(et) * ut;
+            const R uu = un * un + ut * ut;
+            // e.u/c_s^2 + (e.u)^2/(2 c_s^4) - u^2/(2 c_s^2) with c_s^2 = 1/3
+            const R q = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
+            // Eq. (29) at the point and Eq. (33) with the face density
+            const R feq = w9 * p + (w9 / R(3)) * rho_pt * q;
+            p_f += feq;
+            if (en != 0) m_n += R(en) * feq;
+            if (et != 0) m_t += R(et) * feq;
+            if (en != 0) {
+                const R feqm = w9 * p + (w9 / R(3)) * rho_f * q;
+                SMn += feqm;
+                if (et != 0) SMt += R(en * et) * feqm;
+            }
+            if (in_hg) {
+                const R mu = base[VMU] - R(et) * dd[VMU];
+                // Eq. (42)
+                R geq;
+                if (en == 0 && et == 0)
+                    geq = C - R(3) * mu * Q * (R(1) - wh);
+                else
+                    geq = R(3) * wh * (mu * Q + C * eu);
+                C_new += geq;
+                if (en != 0) {
+                    SG += R(en) * geq;
+                    // Eq. (9), alpha != 0
+                    const R T = base[VT] - R(et) * dd[VT];
+                    const R cp_pt = mix<R>(P.cp, Cc, Fsc);
+                    const R heq = wh * (cpref * T + cp_pt * T * q);
+                    SH += R(en) * heq;
+                }
+            }
+        }
+    }
+    // Eq. (56): new face state; equilibria at the face have closed-form moments
+    const R inv_rho = R(1) / rho_f;
+    const R un_f = R(3) * m_n * inv_rho;
+    const R ut_f = R(3) * m_t * inv_rho;
+    const R a_h = R(P.k_h) * lam_f * inv_rho;
+    const R a_f = R(P.k_f) * mu_f * inv_rho;
+    const R a_g = R(P.a_g);
+    const R T_f = M[VT];
+    F[0] = (R(1) - a_h) * cp_f * T_f * un_f + a_h * SH;
+    F[1] = m_n;
+    F[2] = (R(1) - a_f) * (p_f + rho_f * un_f * un_f) * R(1.0 / 3.0) + a_f * SMn;
+    F[3] = (R(1) - a_f) * rho_f * un_f * ut_f * R(1.0 / 3.0) + a_f * SMt;
+    F[4] = (R(1) - a_g) * C_new * un_f + a_g * SG;
+}
+
+// Wall-face conditions: no mass flux through an impermeable wall, no
+// phase-field flux, no heat flux through an adiabatic wall.
+template <typename R>
+__device__ __forceinline__ void wall_face(const DevParams& P, int side, R F[5])
+{
+    if (P.flow[side] != FLOW_OUTLET) F[1] = R(0);
+    F[4] = R(0);
+    if (P.heat[side] == HEAT_ADIABATIC) F[0] = R(0);
+}
+
+// Source vector F_E of Eq. (51) (with the C source in row 5) at one cell.
+// c: the cell's primitives (with rho at NPRIM), dux.. central differences.
+template <typename R>
+__device__ __forceinline__ void sources(const DevParams& P, const R c[NPRIM + 1], R Fl, R fsdot, R dudx,
+                                        R dvdy, R drhodx, R drhody, R dmudx, R dmudy, R S[5])
+{
+    const R rho = c[NPRIM];
+    const R u = c[VU], v = c[VV], C = c[VC];
+    const R cp = mix<R>(P.cp, clamp01(C), c[VFS]);
+    const R ex = R(P.expansion);
+    const R surf = P.surf_model == 1 ? -Fl * C : -C;
+    S[0] = cp * c[VT] * (dudx + dvdy);
+    S[1] = (u * drhodx + v * drhody) * R(1.0 / 3.0) + rho * R(1.0 / 3.0) * ex * fsdot;
+    S[2] = R(1.0 / 3.0) * (surf * dmudx - rho * u * fsdot + rho * R(P.gx));
+    S[3] = R(1.0 / 3.0) * (surf * dmudy - rho * v * fsdot + rho * R(P.gy));
+    S[4] = C * ex * fsdot;
+}
+
+}  // namespace eulbfs

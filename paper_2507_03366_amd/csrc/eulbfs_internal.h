@@ -1,0 +1,52 @@
+// Internal interface between the C-ABI runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "eulbfs_device.h"
+
+namespace eulbfs {
+
+// Shu-Osher SSP-RK3 stage (Eq. 58): W_out = ca W^n + cb W^(k) + cc dt R(W^(k)).
+struct StageCoef {
+    double ca, cb, cc;
+    int last;  // third stage: also write the lagged dF_s/dt
+};
+
+// Intermediate planes of the split path (ghosted grid of (nx+6) x (ny+6)).
+template <typename R>
+struct SplitScratch {
+    State<R> g;      // ghosted conserved state
+    int gpitch;
+    R* prim;         // NPRIM + 1 planes (T, C, F_s, u, v, p, mu_c, rho), ghosted
+    size_t pstride;  // elements between prim planes
+    R* Fx;           // 5 planes, (ny) rows of fpitch, x-face i at column i
+    R* Fy;           // 5 planes, (ny + 1) rows of fpitch
+    int fpitch;
+    size_t fstride;  // elements between flux planes
+};
+
+enum { TILE_32x8 = 0, TILE_64x4 = 1, TILE_16x16 = 2, TILE_64x8 = 3, NTILES = 4 };
+
+constexpr int NRED = 7;  // sum rho, sum C, sum H, sum F_s, max |u|, non-finite, tip column
+
+template <typename R>
+hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,
+                              const State<R>& Wn, const State<R>& out, R* fsdot, hipStream_t st);
+template <typename R>
+hipError_t launch_stage_split(const DevParams& P, const SplitScratch<R>& X, const StageCoef& K, const State<R>& in,
+                              const State<R>& Wn, const State<R>& out, R* fsdot, R* resid, size_t resid_stride,
+                              hipStream_t st);
+template <typename R>
+hipError_t launch_init(const DevParams& P, const double* prim6, const State<R>& out, R* fsdot, hipStream_t st);
+template <typename R>
+hipError_t launch_set_conserved(const DevParams& P, const double* w6, const State<R>& out, R* fsdot, int which,
+                                hipStream_t st);
+template <typename R>
+hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, int what, double* dst,
+                         hipStream_t st);
+template <typename R>
+hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,
+                         hipStream_t st);
+
+}  // namespace eulbfs

@@ -1,0 +1,631 @@
+// HIP kernels of the EULBFS time step for gfx950 (MI355X).
+//
+//   k_stage_fused   one SSP-RK3 stage (Eq. 58) of a whole grid: a 2-D tile of
+//                   cells per workgroup stages W of the tile plus three halo
+//                   layers in LDS (boundary rules applied on the fly at the
+//                   domain edge), recovers the primitive fields (Eqs. 5-7),
+//                   mu_c, computes every face flux of the tile once (Eqs.
+//                   53-56), then updates its cells with the sources of Eq. (51),
+//                   the RK combination and the momentum projection.
+//   k_fill_ghosts / k_split_prims / k_split_faces / k_split_update
+//                   the same stage in four kernels with the intermediate
+//                   fields in HBM (ghosted state, primitive planes, face flux
+//                   planes); used for face-by-face checks and as a variant.
+//   k_init          primitive initial fields -> conserved vector.
+//   k_export        conserved or derived field -> dense double plane.
+//   k_reduce_*      FP64 integrals, deterministic two-pass wave reduction.
+#include "eulbfs_device.h"
+#include "eulbfs_internal.h"
+
+namespace eulbfs {
+
+// ---------------------------------------------------------------------------
+// Per-cell update shared by the fused and the split stage kernels.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef& K, const R c[NPRIM + 1],
+                                            const Cons<R>& Wk, R dudx, R dvdy, R drhodx, R drhody, R dmudx,
+                                            R dmudy, const R dF[5], const State<R>& Wn, const State<R>& out,
+                                            R* fsdot, R* resid, size_t resid_stride, size_t q)
+{
+    R Fl = R(0);
+    if (P.surf_model == 1) {
+        double fl, T;
+        closure(P, Wk.H, clamp01((double)Wk.C), fl, T);
+        Fl = R(fl);
+    }
+    const R fsd = fsdot[q];
+    R S[5];
+    sources(P, c, Fl, fsd, dudx, dvdy, drhodx, drhody, dmudx, dmudy, S);
+    R res[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) res[k] = -dF[k] + S[k];
+    if (resid) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) resid[k * resid_stride + q] = res[k];
+        return;
+    }
+    Cons<R> wn = Wk;
+    if (K.ca != 0.0) wn = read_cell(Wn, P.pitch, (int)(q % P.pitch), (int)(q / P.pitch));
+    const double cdt = K.cc * P.dt;
+    const double Hnew = K.ca * wn.H + K.cb * Wk.H + cdt * (double)res[0];
+    const R ca = R(K.ca), cb = R(K.cb), cdtr = R(cdt);
+    const R pnew = ca * wn.p + cb * Wk.p + cdtr * res[1];
+    R mxnew = ca * wn.mx + cb * Wk.mx + cdtr * res[2];
+    R mynew = ca * wn.my + cb * Wk.my + cdtr * res[3];
+    const R Cnew = ca * wn.C + cb * Wk.C + cdtr * res[4];
+    // rigid solid: M <- (1 - F_s) M with F_s of the new stage value
+    const double Fs_new = solid_fraction(P, Hnew, (double)Cnew);
+    mxnew *= R(1.0 - Fs_new);
+    mynew *= R(1.0 - Fs_new);
+    out.H[q] = Hnew;
+    out.p[q] = pnew;
+    out.mx[q] = mxnew;
+    out.my[q] = mynew;
+    out.C[q] = Cnew;
+    if (K.last) fsdot[q] = R((Fs_new - solid_fraction(P, wn.H, (double)wn.C)) * P.inv_dt);
+}
+
+// ---------------------------------------------------------------------------
+// Fused stage kernel.
+// ---------------------------------------------------------------------------
+template <typename R, int LAT, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    k_stage_fused(DevParams P, StageCoef K, State<R> in, State<R> Wn, State<R> out, R* fsdot)
+{
+    constexpr int NT = TX * TY;
+    constexpr int W3 = TX + 2 * NG, H3 = TY + 2 * NG;
+    constexpr int W2 = TX + 4, H2 = TY + 4;
+    constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+    __shared__ double sH[W3 * H3];
+    __shared__ R sW[4][W3 * H3];
+    __shared__ R sP[NPRIM + 1][W2 * H2];
+    __shared__ R sF[5][NFX + NFY];
+
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+
+    // 1. stage W of the tile and three halo layers
+    for (int q = tid; q < W3 * H3; q += NT) {
+        const int li = q % W3, lj = q / W3;
+        const Cons<R> w = load_bc(P, in, i0 + li - NG, j0 + lj - NG);
+        sH[q] = w.H;
+        sW[0][q] = w.p;
+        sW[1][q] = w.mx;
+        sW[2][q] = w.my;
+        sW[3][q] = w.C;
+    }
+    __syncthreads();
+
+    // 2. primitives and mu_c on the tile and two halo layers
+    for (int q = tid; q < W2 * H2; q += NT) {
+        const int li = q % W2, lj = q / W2;
+        const int q3 = (lj + 1) * W3 + li + 1;
+        Cons<R> w;
+        w.H = sH[q3];
+        w.p = sW[0][q3];
+        w.mx = sW[1][q3];
+        w.my = sW[2][q3];
+        w.C = sW[3][q3];
+        R pr[NPRIM + 1];
+        primitives(P, w, pr);
+        pr[VMU] = chem_potential(P, w.C, sW[3][q3 + 1], sW[3][q3 - 1], sW[3][q3 + W3], sW[3][q3 - W3]);
+#pragma unroll
+        for (int k = 0; k <= NPRIM; ++k) sP[k][q] = pr[k];
+    }
+    __syncthreads();
+
+    // 3. every face of the tile once
+    const R i2dx = R(P.inv_2dx);
+    for (int f = tid; f < NFX + NFY; f += NT) {
+        R va[NPRIM], gna[NPRIM], gta[NPRIM], vb[NPRIM], gnb[NPRIM], gtb[NPRIM], F[5];
+        if (f < NFX) {
+            const int fi = f % (TX + 1), fj = f / (TX + 1);
+            const int a = (fj + 2) * W2 + fi + 1, b = a + 1;
+#pragma unroll
+            for (int k = 0; k < NPRIM; ++k) {
+                va[k] = sP[k][a];
+                gna[k] = (sP[k][a + 1] - sP[k][a - 1]) * i2dx;
+                gta[k] = (sP[k][a + W2] - sP[k][a - W2]) * i2dx;
+                vb[k] = sP[k][b];
+                gnb[k] = (sP[k][b + 1] - sP[k][b - 1]) * i2dx;
+                gtb[k] = (sP[k][b + W2] - sP[k][b - W2]) * i2dx;
+            }
+            face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+            const int gi = i0 + fi;
+            if (!P.periodic_x) {
+                if (gi == 0) wall_face(P, 0, F);
+                else if (gi == P.nx) wall_face(P, 1, F);
+            }
+            sF[0][f] = F[0];
+            sF[1][f] = F[1];
+            sF[2][f] = F[2];
+            sF[3][f] = F[3];
+            sF[4][f] = F[4];
+        } else {
+            const int g = f - NFX;
+            const int fi = g % TX, fj = g / TX;
+            const int a = (fj + 1) * W2 + fi + 2, b = a + W2;
+#pragma unroll
+            for (int k = 0; k < NPRIM; ++k) {
+                const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
+                va[k] = sP[ks][a];
+                gna[k] = (sP[ks][a + W2] - sP[ks][a - W2]) * i2dx;
+                gta[k] = (sP[ks][a + 1] - sP[ks][a - 1]) * i2dx;
+                vb[k] = sP[ks][b];
+                gnb[k] = (sP[ks][b + W2] - sP[ks][b - W2]) * i2dx;
+                gtb[k] = (sP[ks][b + 1] - sP[ks][b - 1]) * i2dx;
+            }
+            face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+            const int gj = j0 + fj;
+            if (!P.periodic_y) {
+                if (gj == 0) wall_face(P, 2, F);
+                else if (gj == P.ny) wall_face(P, 3, F);
+            }
+            sF[0][f] = F[0];
+            sF[1][f] = F[1];
+            sF[2][f] = F[3];  // x-momentum flux through a y-face: sum e_y e_x f*
+            sF[3][f] = F[2];
+            sF[4][f] = F[4];
+        }
+    }
+    __syncthreads();
+
+    // 4. cell update
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i >= P.nx || j >= P.ny) return;
+    const int fl = ty * (TX + 1) + tx;
+    const int fb = NFX + ty * TX + tx;
+    const R idx = R(1.0 / P.dx);
+    R dF[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) dF[k] = (sF[k][fl + 1] - sF[k][fl]) * idx + (sF[k][fb + TX] - sF[k][fb]) * idx;
+    const int c2 = (ty + 2) * W2 + tx + 2;
+    R c[NPRIM + 1];
+#pragma unroll
+    for (int k = 0; k <= NPRIM; ++k) c[k] = sP[k][c2];
+    const R dudx = (sP[VU][c2 + 1] - sP[VU][c2 - 1]) * i2dx;
+    const R dvdy = (sP[VV][c2 + W2] - sP[VV][c2 - W2]) * i2dx;
+    const R drx = (sP[NPRIM][c2 + 1] - sP[NPRIM][c2 - 1]) * i2dx;
+    const R dry = (sP[NPRIM][c2 + W2] - sP[NPRIM][c2 - W2]) * i2dx;
+    const R dmx = (sP[VMU][c2 + 1] - sP[VMU][c2 - 1]) * i2dx;
+    const R dmy = (sP[VMU][c2 + W2] - sP[VMU][c2 - W2]) * i2dx;
+    const int c3 = (ty + NG) * W3 + tx + NG;
+    Cons<R> wk;
+    wk.H = sH[c3];
+    wk.p = sW[0][c3];
+    wk.mx = sW[1][c3];
+    wk.my = sW[2][c3];
+    wk.C = sW[3][c3];
+    const size_t q = (size_t)j * P.pitch + i;
+    cell_update(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, (R*)nullptr, 0, q);
+}
+
+// ---------------------------------------------------------------------------
+// Split path.  Ghosted planes have (ny + 6) rows of gpitch elements; cell
+// (i, j) sits at (j + 3) * gpitch + i + 3.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_fill_ghosts(DevParams P, State<R> in, State<R> g, int gpitch)
+{
+    const int li = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lj = blockIdx.y * blockDim.y + threadIdx.y;
+    if (li >= P.nx + 2 * NG || lj >= P.ny + 2 * NG) return;
+    const Cons<R> w = load_bc(P, in, li - NG, lj - NG);
+    const size_t q = (size_t)lj * gpitch + li;
+    g.H[q] = w.H;
+    g.p[q] = w.p;
+    g.mx[q] = w.mx;
+    g.my[q] = w.my;
+    g.C[q] = w.C;
+}
+
+template <typename R>
+__global__ void k_split_prims(DevParams P, State<R> g, int gpitch, R* prim, size_t pstride)
+{
+    const int li = blockIdx.x * blockDim.x + threadIdx.x + 1;  // ring 2 of the ghosted grid
+    const int lj = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    if (li >= P.nx + 2 * NG - 1 || lj >= P.ny + 2 * NG - 1) return;
+    const size_t q = (size_t)lj * gpitch + li;
+    Cons<R> w;
+    w.H = g.H[q];
+    w.p = g.p[q];
+    w.mx = g.mx[q];
+    w.my = g.my[q];
+    w.C = g.C[q];
+    R pr[NPRIM + 1];
+    primitives(P, w, pr);
+    pr[VMU] = chem_potential(P, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]);
+#pragma unroll
+    for (int k = 0; k <= NPRIM; ++k) prim[k * pstride + q] = pr[k];
+}
+
+template <typename R, int LAT>
+__global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gpitch, R* Fx, R* Fy, int fpitch,
+                              size_t fstride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const R i2dx = R(P.inv_2dx);
+    R va[NPRIM], gna[NPRIM], gta[NPRIM], vb[NPRIM], gnb[NPRIM], gtb[NPRIM], F[5];
+    if (i <= P.nx && j < P.ny) {  // x-face i between cells i-1 and i
+        const size_t a = (size_t)(j + NG) * gpitch + (i - 1 + NG), b = a + 1;
+#pragma unroll
+        for (int k = 0; k < NPRIM; ++k) {
+            const R* pk = prim + k * pstride;
+            va[k] = pk[a];
+            gna[k] = (pk[a + 1] - pk[a - 1]) * i2dx;
+            gta[k] = (pk[a + gpitch] - pk[a - gpitch]) * i2dx;
+            vb[k] = pk[b];
+            gnb[k] = (pk[b + 1] - pk[b - 1]) * i2dx;
+            gtb[k] = (pk[b + gpitch] - pk[b - gpitch]) * i2dx;
+        }
+        face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+        if (!P.periodic_x) {
+            if (i == 0) wall_face(P, 0, F);
+            else if (i == P.nx) wall_face(P, 1, F);
+        }
+        const size_t o = (size_t)j * fpitch + i;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Fx[k * fstride + o] = F[k];
+    }
+    if (i < P.nx && j <= P.ny) {  // y-face j between cells j-1 and j
+        const size_t a = (size_t)(j - 1 + NG) * gpitch + (i + NG), b = a + gpitch;
+#pragma unroll
+        for (int k = 0; k < NPRIM; ++k) {
+            const int ks = k == VU ? VV : (k == VV ? VU : k);
+            const R* pk = prim + ks * pstride;
+            va[k] = pk[a];
+            gna[k] = (pk[a + gpitch] - pk[a - gpitch]) * i2dx;
+            gta[k] = (pk[a + 1] - pk[a - 1]) * i2dx;
+            vb[k] = pk[b];
+            gnb[k] = (pk[b + gpitch] - pk[b - gpitch]) * i2dx;
+            gtb[k] = (pk[b + 1] - pk[b - 1]) * i2dx;
+        }
+        face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+        if (!P.periodic_y) {
+            if (j == 0) wall_face(P, 2, F);
+            else if (j == P.ny) wall_face(P, 3, F);
+        }
+        const size_t o = (size_t)j * fpitch + i;
+        Fy[0 * fstride + o] = F[0];
+        Fy[1 * fstride + o] = F[1];
+        Fy[2 * fstride + o] = F[3];
+        Fy[3 * fstride + o] = F[2];
+        Fy[4 * fstride + o] = F[4];
+    }
+}
+
+template <typename R>
+__global__ void k_split_update(DevParams P, StageCoef K, const R* prim, size_t pstride, int gpitch, const R* Fx,
+                               const R* Fy, int fpitch, size_t fstride, State<R> in, State<R> Wn, State<R> out,
+                               R* fsdot, R* resid, size_t resid_stride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const R idx = R(1.0 / P.dx);
+    const size_t o = (size_t)j * fpitch + i;
+    R dF[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        dF[k] = (Fx[k * fstride + o + 1] - Fx[k * fstride + o]) * idx +
+                (Fy[k * fstride + o + fpitch] - Fy[k * fstride + o]) * idx;
+    const size_t c2 = (size_t)(j + NG) * gpitch + i + NG;
+    R c[NPRIM + 1];
+#pragma unroll
+    for (int k = 0; k <= NPRIM; ++k) c[k] = prim[k * pstride + c2];
+    const R i2dx = R(P.inv_2dx);
+    const R* pu = prim + VU * pstride;
+    const R* pv = prim + VV * pstride;
+    const R* pr = prim + NPRIM * pstride;
+    const R* pm = prim + VMU * pstride;
+    const R dudx = (pu[c2 + 1] - pu[c2 - 1]) * i2dx;
+    const R dvdy = (pv[c2 + gpitch] - pv[c2 - gpitch]) * i2dx;
+    const R drx = (pr[c2 + 1] - pr[c2 - 1]) * i2dx;
+    const R dry = (pr[c2 + gpitch] - pr[c2 - gpitch]) * i2dx;
+    const R dmx = (pm[c2 + 1] - pm[c2 - 1]) * i2dx;
+    const R dmy = (pm[c2 + gpitch] - pm[c2 - gpitch]) * i2dx;
+    const size_t q = (size_t)j * P.pitch + i;
+    const Cons<R> wk = read_cell(in, P.pitch, i, j);
+    cell_update(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, resid, resid_stride, q);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state, export, set
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_init(DevParams P, const double* prim6, State<R> out, R* fsdot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const size_t n = (size_t)P.nx * P.ny, s = (size_t)j * P.nx + i;
+    const double T = prim6[s], Fl = prim6[n + s], C = prim6[2 * n + s];
+    const double u = prim6[3 * n + s], v = prim6[4 * n + s], p = prim6[5 * n + s];
+    const double H = enthalpy_of(P, T, Fl, C);
+    const double Cc = clamp01(C);
+    const double Fs = solid_fraction(P, H, C);
+    const double rho = mix<double>(P.rho, Cc, Fs);
+    const size_t q = (size_t)j * P.pitch + i;
+    out.H[q] = H;
+    out.p[q] = R(p);
+    out.mx[q] = R(rho / 3.0 * u);
+    out.my[q] = R(rho / 3.0 * v);
+    out.C[q] = R(C);
+    fsdot[q] = R(0);
+}
+
+template <typename R>
+__global__ void k_set_conserved(DevParams P, const double* w6, State<R> out, R* fsdot, int which)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const size_t n = (size_t)P.nx * P.ny, s = (size_t)j * P.nx + i;
+    const size_t q = (size_t)j * P.pitch + i;
+    // which: -1 all six planes, else one plane (0..5) read from w6[0..n)
+    for (int k = 0; k < 6; ++k) {
+        if (which >= 0 && k != which) continue;
+        const double x = which >= 0 ? w6[s] : w6[k * n + s];
+        switch (k) {
+            case 0: out.H[q] = x; break;
+            case 1: out.p[q] = R(x); break;
+            case 2: out.mx[q] = R(x); break;
+            case 3: out.my[q] = R(x); break;
+            case 4: out.C[q] = R(x); break;
+            default: fsdot[q] = R(x); break;
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_export(DevParams P, State<R> S, const R* fsdot, int what, double* dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const size_t q = (size_t)j * P.pitch + i, s = (size_t)j * P.nx + i;
+    const Cons<R> w = read_cell(S, P.pitch, i, j);
+    double x = 0.0;
+    if (what <= 5) {
+        switch (what) {
+            case 0: x = w.H; break;
+            case 1: x = w.p; break;
+            case 2: x = w.mx; break;
+            case 3: x = w.my; break;
+            case 4: x = w.C; break;
+            default: x = fsdot[q]; break;
+        }
+    } else if (what == 12) {
+        const R cE = load_bc(P, S, i + 1, j).C, cW = load_bc(P, S, i - 1, j).C;
+        const R cN = load_bc(P, S, i, j + 1).C, cS = load_bc(P, S, i, j - 1).C;
+        x = chem_potential(P, w.C, cE, cW, cN, cS);
+    } else {
+        const double Cc = clamp01((double)w.C);
+        double Fl, T;
+        closure(P, w.H, Cc, Fl, T);
+        const double Fs = Cc * (1.0 - Fl);
+        const double rho = (double)mix<R>(P.rho, R(Cc), R(Fs));
+        switch (what) {
+            case 6: x = T; break;
+            case 7: x = Fl; break;
+            case 8: x = Fs; break;
+            case 9: x = rho; break;
+            case 10: x = (double)(w.mx * (R(3) / R(rho))); break;
+            default: x = (double)(w.my * (R(3) / R(rho))); break;
+        }
+    }
+    dst[s] = x;
+}
+
+template <typename R>
+__global__ void k_export_ghosted(DevParams P, State<R> S, double* dst, int gnx, int gny)
+{
+    const int li = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lj = blockIdx.y * blockDim.y + threadIdx.y;
+    if (li >= gnx || lj >= gny) return;
+    const Cons<R> w = load_bc(P, S, li - NG, lj - NG);
+    const size_t n = (size_t)gnx * gny, s = (size_t)lj * gnx + li;
+    dst[s] = w.H;
+    dst[n + s] = w.p;
+    dst[2 * n + s] = w.mx;
+    dst[3 * n + s] = w.my;
+    dst[4 * n + s] = w.C;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions: per-block partials in a fixed order, then
+// one block sums the partials in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// partial layout: [block][NRED]: sum rho, sum C, sum H, sum Fs, max|u|, nonfinite, tip
+template <typename R>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(DevParams P, State<R> S, double* partial)
+{
+    __shared__ double sred[RED_THREADS / 64][NRED];
+    double acc[NRED] = {0, 0, 0, 0, 0, 0, 0};
+    const size_t n = (size_t)P.nx * P.ny;
+    const int ic = P.nx / 2;
+    for (size_t s = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; s < n; s += (size_t)gridDim.x * RED_THREADS) {
+        const int i = (int)(s % P.nx), j = (int)(s / P.nx);
+        const Cons<R> w = read_cell(S, P.pitch, i, j);
+        const double Cc = clamp01((double)w.C);
+        double Fl, T;
+        closure(P, w.H, Cc, Fl, T);
+        const double Fs = Cc * (1.0 - Fl);
+        const double rho = mix<double>(P.rho, Cc, Fs);
+        const double u = 3.0 * (double)w.mx / rho, v = 3.0 * (double)w.my / rho;
+        acc[0] += rho;
+        acc[1] += (double)w.C;
+        acc[2] += w.H;
+        acc[3] += Fs;
+        acc[4] = fmax(acc[4], sqrt(u * u + v * v));
+        const bool finite = isfinite(w.H) && isfinite((double)w.p) && isfinite((double)w.mx) &&
+                            isfinite((double)w.my) && isfinite((double)w.C);
+        acc[5] += finite ? 0.0 : 1.0;
+        if (i == ic) acc[6] += Fs;
+    }
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) {
+        const double r = k == 4 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) sred[wv][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        const int k = threadIdx.x;
+        double r = sred[0][k];
+        for (int w = 1; w < RED_THREADS / 64; ++w) r = k == 4 ? fmax(r, sred[w][k]) : r + sred[w][k];
+        partial[(size_t)blockIdx.x * NRED + k] = r;
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* partial, int nblocks, double* out)
+{
+    __shared__ double sred[RED_THREADS / 64][NRED];
+    double acc[NRED] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+        for (int k = 0; k < NRED; ++k)
+            acc[k] = k == 4 ? fmax(acc[k], partial[(size_t)b * NRED + k]) : acc[k] + partial[(size_t)b * NRED + k];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) {
+        const double r = k == 4 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) sred[wv][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        const int k = threadIdx.x;
+        double r = sred[0][k];
+        for (int w = 1; w < RED_THREADS / 64; ++w) r = k == 4 ? fmax(r, sred[w][k]) : r + sred[w][k];
+        out[k] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+static inline dim3 grid2(int nx, int ny, dim3 b) { return dim3((nx + b.x - 1) / b.x, (ny + b.y - 1) / b.y); }
+
+template <typename R, int LAT, int TX, int TY>
+static hipError_t launch_fused_t(const DevParams& P, const StageCoef& K, const State<R>& in, const State<R>& Wn,
+                                 const State<R>& out, R* fsdot, hipStream_t st)
+{
+    dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((k_stage_fused<R, LAT, TX, TY>), grid, dim3(TX * TY), 0, st, P, K, in, Wn, out, fsdot);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,
+                              const State<R>& Wn, const State<R>& out, R* fsdot, hipStream_t st)
+{
+    if (P.lattice_hg == 5) {
+        switch (tile) {
+            case TILE_64x4: return launch_fused_t<R, 5, 64, 4>(P, K, in, Wn, out, fsdot, st);
+            case TILE_16x16: return launch_fused_t<R, 5, 16, 16>(P, K, in, Wn, out, fsdot, st);
+            case TILE_64x8: return launch_fused_t<R, 5, 64, 8>(P, K, in, Wn, out, fsdot, st);
+            default: return launch_fused_t<R, 5, 32, 8>(P, K, in, Wn, out, fsdot, st);
+        }
+    }
+    switch (tile) {
+        case TILE_64x4: return launch_fused_t<R, 9, 64, 4>(P, K, in, Wn, out, fsdot, st);
+        case TILE_16x16: return launch_fused_t<R, 9, 16, 16>(P, K, in, Wn, out, fsdot, st);
+        case TILE_64x8: return launch_fused_t<R, 9, 64, 8>(P, K, in, Wn, out, fsdot, st);
+        default: return launch_fused_t<R, 9, 32, 8>(P, K, in, Wn, out, fsdot, st);
+    }
+}
+
+template <typename R>
+hipError_t launch_stage_split(const DevParams& P, const SplitScratch<R>& X, const StageCoef& K, const State<R>& in,
+                              const State<R>& Wn, const State<R>& out, R* fsdot, R* resid, size_t resid_stride,
+                              hipStream_t st)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_fill_ghosts<R>, grid2(P.nx + 2 * NG, P.ny + 2 * NG, b), b, 0, st, P, in, X.g, X.gpitch);
+    hipLaunchKernelGGL(k_split_prims<R>, grid2(P.nx + 4, P.ny + 4, b), b, 0, st, P, X.g, X.gpitch, X.prim,
+                       X.pstride);
+    if (P.lattice_hg == 5)
+        hipLaunchKernelGGL((k_split_faces<R, 5>), grid2(P.nx + 1, P.ny + 1, b), b, 0, st, P, (const R*)X.prim,
+                           X.pstride, X.gpitch, X.Fx, X.Fy, X.fpitch, X.fstride);
+    else
+        hipLaunchKernelGGL((k_split_faces<R, 9>), grid2(P.nx + 1, P.ny + 1, b), b, 0, st, P, (const R*)X.prim,
+                           X.pstride, X.gpitch, X.Fx, X.Fy, X.fpitch, X.fstride);
+    hipLaunchKernelGGL(k_split_update<R>, grid2(P.nx, P.ny, b), b, 0, st, P, K, (const R*)X.prim, X.pstride,
+                       X.gpitch, (const R*)X.Fx, (const R*)X.Fy, X.fpitch, X.fstride, in, Wn, out, fsdot, resid,
+                       resid_stride);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_init(const DevParams& P, const double* prim6, const State<R>& out, R* fsdot, hipStream_t st)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_init<R>, grid2(P.nx, P.ny, b), b, 0, st, P, prim6, out, fsdot);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_set_conserved(const DevParams& P, const double* w6, const State<R>& out, R* fsdot, int which,
+                                hipStream_t st)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_set_conserved<R>, grid2(P.nx, P.ny, b), b, 0, st, P, w6, out, fsdot, which);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, int what, double* dst,
+                         hipStream_t st)
+{
+    const dim3 b(64, 4);
+    if (what == 14) {
+        hipLaunchKernelGGL(k_export_ghosted<R>, grid2(P.nx + 2 * NG, P.ny + 2 * NG, b), b, 0, st, P, S, dst,
+                           P.nx + 2 * NG, P.ny + 2 * NG);
+    } else {
+        hipLaunchKernelGGL(k_export<R>, grid2(P.nx, P.ny, b), b, 0, st, P, S, fsdot, what, dst);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_partial<R>, dim3(nblocks), dim3(RED_THREADS), 0, st, P, S, partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, st, (const double*)partial, nblocks, out);
+    return hipGetLastError();
+}
+
+#define EULBFS_INSTANTIATE(R)                                                                                      \
+    template hipError_t launch_stage_fused<R>(const DevParams&, int, const StageCoef&, const State<R>&,            \
+                                              const State<R>&, const State<R>&, R*, hipStream_t);                  \
+    template hipError_t launch_stage_split<R>(const DevParams&, const SplitScratch<R>&, const StageCoef&,          \
+                                              const State<R>&, const State<R>&, const State<R>&, R*, R*, size_t,   \
+                                              hipStream_t);                                                        \
+    template hipError_t launch_init<R>(const DevParams&, const double*, const State<R>&, R*, hipStream_t);         \
+    template hipError_t launch_set_conserved<R>(const DevParams&, const double*, const State<R>&, R*, int,         \
+                                                hipStream_t);                                                      \
+    template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
+    template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);
+
+EULBFS_INSTANTIATE(double)
+EULBFS_INSTANTIATE(float)
+
+}  // namespace eulbfs

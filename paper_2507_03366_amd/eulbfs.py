@@ -1,0 +1,274 @@
+"""Python binding of the C ABI in include/eulbfs.h (ctypes).
+
+The functions keep the C names and only marshal arguments; every step of the
+solver runs in the HIP kernels of libeulbfs.so.  PyTorch is used only to hold
+device memory (the workspace) and to name the HIP stream.  There is no CPU
+fallback: importing this module without a built libeulbfs.so raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeulbfs.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+KERNEL_FUSED, KERNEL_SPLIT = 0, 1
+INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
+ABI_VERSION = 1
+FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
+             W_GHOSTED=14)
+SCALAR_DIAG = 100
+NDIAG = 10
+DIAG_NAMES = ("mass", "volume_C", "enthalpy", "solid", "umax", "nonfinite", "tip", "time", "steps", "dt")
+
+
+class EulbfsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"eulbfs error {code}: {msg}")
+        self.code = code
+
+
+class eulbfs_bc(ct.Structure):
+    _fields_ = [("periodic", ct.c_int32), ("flow", ct.c_int32), ("heat", ct.c_int32), ("reserved", ct.c_int32),
+                ("T_w", ct.c_double), ("theta_deg", ct.c_double)]
+
+
+class eulbfs_params(ct.Structure):
+    _fields_ = [
+        ("struct_size", ct.c_uint32), ("abi_version", ct.c_uint32),
+        ("nx", ct.c_int32), ("ny", ct.c_int32), ("lattice_hg", ct.c_int32), ("precision", ct.c_int32),
+        ("kernel", ct.c_int32), ("surf_model", ct.c_int32),
+        ("dx", ct.c_double), ("delta_t", ct.c_double), ("dt", ct.c_double),
+        ("rho", ct.c_double * 3), ("mu", ct.c_double * 3), ("lambda_", ct.c_double * 3), ("cp", ct.c_double * 3),
+        ("latent", ct.c_double), ("T_s", ct.c_double), ("T_l", ct.c_double),
+        ("sigma", ct.c_double), ("xi", ct.c_double), ("mobility", ct.c_double), ("Qg", ct.c_double),
+        ("gx", ct.c_double), ("gy", ct.c_double),
+        ("bc", eulbfs_bc * 4),
+        ("tile_x", ct.c_int32), ("tile_y", ct.c_int32), ("reserved", ct.c_int32 * 6),
+    ]
+
+
+class eulbfs_init(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("on_device", ct.c_int32), ("planes", ct.POINTER(ct.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libeulbfs.so (built in-tree by paper_2507_03366_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2507_03366_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        vp, dp, sz = ct.c_void_p, ct.POINTER(ct.c_double), ct.c_size_t
+        pp = ct.POINTER(eulbfs_params)
+        L.eulbfs_check_params.argtypes = [pp, ct.c_char_p, sz]
+        L.eulbfs_workspace_bytes.argtypes = [pp]
+        L.eulbfs_workspace_bytes.restype = sz
+        L.eulbfs_create.argtypes = [pp, ct.POINTER(eulbfs_init), vp, sz, vp, ct.POINTER(vp)]
+        L.eulbfs_step.argtypes = [vp, ct.c_int64]
+        L.eulbfs_run.argtypes = [vp, ct.c_int64]
+        L.eulbfs_query.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
+        L.eulbfs_set_field.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
+        L.eulbfs_residual.argtypes = [vp, dp, dp, dp, ct.c_int32]
+        L.eulbfs_destroy.argtypes = [vp]
+        L.eulbfs_last_error.argtypes = [vp]
+        L.eulbfs_last_error.restype = ct.c_char_p
+        for f in ("eulbfs_check_params", "eulbfs_create", "eulbfs_step", "eulbfs_run", "eulbfs_query",
+                  "eulbfs_set_field", "eulbfs_residual", "eulbfs_destroy"):
+            getattr(L, f).restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def _raise(rc, handle=None):
+    if rc != OK:
+        msg = lib().eulbfs_last_error(handle)
+        raise EulbfsError(rc, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------------------
+# Parameter marshalling
+# ---------------------------------------------------------------------------
+def params_from_problem(pr, precision: int = None, kernel: int = KERNEL_FUSED, tile=(0, 0)) -> eulbfs_params:
+    P = eulbfs_params()
+    P.struct_size = ct.sizeof(eulbfs_params)
+    P.abi_version = ABI_VERSION
+    P.nx, P.ny = pr.nx, pr.ny
+    P.lattice_hg = pr.lattice_hg
+    P.precision = pr.precision if precision is None else precision
+    P.kernel = kernel
+    P.surf_model = pr.surf_model
+    P.dx, P.delta_t, P.dt = pr.dx, pr.delta_t, pr.dt
+    P.rho[:] = list(pr.rho)
+    P.mu[:] = list(pr.mu)
+    P.lambda_[:] = list(pr.lam)
+    P.cp[:] = list(pr.cp)
+    P.latent, P.T_s, P.T_l = pr.latent, pr.T_s, pr.T_l
+    P.sigma, P.xi, P.mobility, P.Qg = pr.sigma, pr.xi, pr.mobility, pr.Qg
+    P.gx, P.gy = pr.gx, pr.gy
+    for k, side in enumerate(("x-", "x+", "y-", "y+")):
+        w = pr.wall(side)
+        if w is None:
+            P.bc[k].periodic = 1
+            P.bc[k].theta_deg = 90.0
+        else:
+            P.bc[k].periodic = 0
+            P.bc[k].flow, P.bc[k].heat = w.flow, w.heat
+            P.bc[k].T_w, P.bc[k].theta_deg = w.T_w, w.theta_deg
+    P.tile_x, P.tile_y = tile
+    return P
+
+
+# ---------------------------------------------------------------------------
+# C-ABI functions (same names; argument marshalling only)
+# ---------------------------------------------------------------------------
+def eulbfs_check_params(P: eulbfs_params) -> str:
+    buf = ct.create_string_buffer(256)
+    rc = lib().eulbfs_check_params(ct.byref(P), buf, 256)
+    return "" if rc == OK else buf.value.decode()
+
+
+def eulbfs_workspace_bytes(P: eulbfs_params) -> int:
+    return int(lib().eulbfs_workspace_bytes(ct.byref(P)))
+
+
+def eulbfs_create(P: eulbfs_params, init_planes, kind: int = INIT_PRIMITIVE, workspace=None, stream=None):
+    """init_planes: float64 array of 6 * nx * ny (host numpy or device torch tensor).
+    workspace: a torch uint8 CUDA tensor of >= eulbfs_workspace_bytes(P) (or None).
+    stream: a torch.cuda.Stream (or None: the default stream).  Returns the handle."""
+    init = eulbfs_init()
+    init.kind = kind
+    if isinstance(init_planes, np.ndarray):
+        arr = np.ascontiguousarray(init_planes, dtype=np.float64)
+        init.on_device = 0
+        init.planes = arr.ctypes.data_as(ct.POINTER(ct.c_double))
+    else:
+        assert init_planes.dtype.itemsize == 8 and init_planes.is_contiguous()
+        init.on_device = 1
+        init.planes = ct.cast(ct.c_void_p(init_planes.data_ptr()), ct.POINTER(ct.c_double))
+    ws_ptr = ct.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = ct.c_void_p(stream.cuda_stream) if stream is not None else None
+    h = ct.c_void_p()
+    _raise(lib().eulbfs_create(ct.byref(P), ct.byref(init), ws_ptr, ws_bytes, st, ct.byref(h)))
+    return h
+
+
+def eulbfs_step(h, nsteps: int) -> None:
+    _raise(lib().eulbfs_step(h, int(nsteps)), h)
+
+
+def eulbfs_run(h, nsteps: int) -> None:
+    _raise(lib().eulbfs_run(h, int(nsteps)), h)
+
+
+def eulbfs_query(h, what: int, nx: int, ny: int) -> np.ndarray:
+    if what == SCALAR_DIAG:
+        out = np.zeros(NDIAG)
+    elif what == FIELD["W_ALL"]:
+        out = np.zeros((6, ny, nx))
+    elif what == FIELD["W_GHOSTED"]:
+        out = np.zeros((5, ny + 6, nx + 6))
+    else:
+        out = np.zeros((ny, nx))
+    _raise(lib().eulbfs_query(h, what, out.ctypes.data_as(ct.c_void_p), out.nbytes, 0), h)
+    return out
+
+
+def eulbfs_set_field(h, what: int, data: np.ndarray) -> None:
+    arr = np.ascontiguousarray(data, dtype=np.float64)
+    _raise(lib().eulbfs_set_field(h, what, arr.ctypes.data_as(ct.c_void_p), arr.nbytes, 0), h)
+
+
+def eulbfs_residual(h, nx: int, ny: int):
+    R = np.zeros((5, ny, nx))
+    Fx = np.zeros((5, ny, nx + 1))
+    Fy = np.zeros((5, ny + 1, nx))
+    dp = ct.POINTER(ct.c_double)
+    _raise(lib().eulbfs_residual(h, R.ctypes.data_as(dp), Fx.ctypes.data_as(dp), Fy.ctypes.data_as(dp), 0), h)
+    return R, Fx, Fy
+
+
+def eulbfs_destroy(h) -> None:
+    lib().eulbfs_destroy(h)
+
+
+def eulbfs_last_error(h=None) -> str:
+    m = lib().eulbfs_last_error(h)
+    return m.decode() if m else ""
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+class Solver:
+    """One grid on the GPU: workspace in a torch uint8 tensor, work on a torch stream."""
+
+    def __init__(self, pr, state=None, *, precision=None, kernel=KERNEL_FUSED, tile=(0, 0), device="cuda:0",
+                 stream=None, conserved=None, own_workspace=True):
+        import torch
+
+        self.pr = pr
+        self.P = params_from_problem(pr, precision=precision, kernel=kernel, tile=tile)
+        msg = eulbfs_check_params(self.P)
+        if msg:
+            raise EulbfsError(EINVAL, msg)
+        self.nx, self.ny = pr.nx, pr.ny
+        self.device = torch.device(device)
+        nbytes = eulbfs_workspace_bytes(self.P)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device) if own_workspace else None
+        ws = None
+        if self.workspace is not None:
+            off = (-self.workspace.data_ptr()) % 256
+            ws = self.workspace[off:off + nbytes]
+        self.stream = stream
+        if conserved is not None:
+            planes, kind = np.ascontiguousarray(conserved, dtype=np.float64).ravel(), INIT_CONSERVED
+        else:
+            planes, kind = np.concatenate([a.ravel() for a in state.planes()]), INIT_PRIMITIVE
+        self.h = eulbfs_create(self.P, planes, kind=kind, workspace=ws, stream=stream)
+
+    def step(self, n: int):
+        eulbfs_step(self.h, n)
+
+    def run(self, n: int):
+        eulbfs_run(self.h, n)
+
+    def field(self, name: str) -> np.ndarray:
+        return eulbfs_query(self.h, FIELD[name], self.nx, self.ny)
+
+    def conserved(self) -> np.ndarray:
+        """(6, ny, nx): H, p, Mx, My, C, dF_s/dt."""
+        return eulbfs_query(self.h, FIELD["W_ALL"], self.nx, self.ny)
+
+    def ghosted(self) -> np.ndarray:
+        return eulbfs_query(self.h, FIELD["W_GHOSTED"], self.nx, self.ny)
+
+    def diagnostics(self) -> dict:
+        d = eulbfs_query(self.h, SCALAR_DIAG, self.nx, self.ny)
+        return dict(zip(DIAG_NAMES, d))
+
+    def residual(self):
+        return eulbfs_residual(self.h, self.nx, self.ny)
+
+    def set_conserved(self, w6: np.ndarray):
+        eulbfs_set_field(self.h, FIELD["W_ALL"], w6)
+
+    def close(self):
+        if self.h is not None:
+            eulbfs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

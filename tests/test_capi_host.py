@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function that include/eulbfs.h declares, and validates parameters."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2507_03366_amd import eulbfs as E
+from paper_2507_03366_amd import problems as PB
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "eulbfs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(eulbfs_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ("eulbfs_create", "eulbfs_step", "eulbfs_run", "eulbfs_query", "eulbfs_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = E.lib()
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_struct_layout_matches_header():
+    # 8 + 6*4 ints, 3 + 12 + 9 doubles, 4 bc of 32 bytes, 8 ints
+    assert ct.sizeof(E.eulbfs_bc) == 32
+    assert ct.sizeof(E.eulbfs_params) == 32 + 24 * 8 + 4 * 32 + 8 * 4
+    assert E.eulbfs_params.dx.offset == 32
+
+
+def _params(**kw):
+    pr, _ = PB.static_droplet(n=64, R=16)
+    return E.params_from_problem(pr.replace(**kw))
+
+
+def test_valid_parameters_pass_and_size_the_workspace():
+    P = _params()
+    assert E.eulbfs_check_params(P) == ""
+    fp64 = E.eulbfs_workspace_bytes(P)
+    # W^n, two RK registers, dF_s/dt: 16 planes of 64 x 64 doubles at least
+    assert fp64 >= 16 * 64 * 64 * 8
+    P32 = E.params_from_problem(PB.static_droplet(n=64, R=16)[0], precision=E.FP32)
+    assert E.eulbfs_workspace_bytes(P32) < fp64
+
+
+@pytest.mark.parametrize("bad, why", [
+    (dict(delta_t=0.6), "delta_t"),
+    (dict(delta_t=0.0), "delta_t"),
+    (dict(lattice_hg=7), "lattice_hg"),
+    (dict(nx=3), "nx"),
+    (dict(rho=(0.9, 1.0, 0.0)), "densities"),
+    (dict(T_s=0.5, T_l=0.0), "T_l"),
+    (dict(xi=0.0), "xi"),
+])
+def test_invalid_parameters_are_rejected(bad, why):
+    P = _params(**bad)
+    msg = E.eulbfs_check_params(P)
+    assert why in msg
+    assert E.eulbfs_workspace_bytes(P) == 0
+    assert why in E.eulbfs_last_error(None)
+
+
+def test_periodic_mismatch_rejected():
+    P = _params()
+    P.bc[0].periodic = 1
+    assert "periodic" in E.eulbfs_check_params(P)
+
+
+def test_abi_guard():
+    P = _params()
+    P.struct_size = 8
+    assert "struct_size" in E.eulbfs_check_params(P)
+    P = _params()
+    P.abi_version = 99
+    assert "abi_version" in E.eulbfs_check_params(P)
+
+
+def test_bad_tile_rejected():
+    P = _params()
+    P.tile_x, P.tile_y = 48, 8
+    assert "tile" in E.eulbfs_check_params(P)
+
+
+def test_create_rejects_before_touching_the_device():
+    P = _params(delta_t=1.0)
+    with pytest.raises(E.EulbfsError) as ei:
+        E.eulbfs_create(P, __import__("numpy").zeros(6 * 64 * 64))
+    assert ei.value.code == E.EINVAL
