@@ -1,0 +1,69 @@
+"""Mutation check of the oracle pins (run by hand; not collected by pytest).
+
+Each entry plants one plausible mistake in a copy of oracle/eulbfs_oracle.c
+(a flipped sign, a dropped term, a swapped index or operand), builds it, and
+runs tests/test_oracle_pins.py against it.  Every mutant must make at least
+one pin fail.
+
+    python tests/oracle_mutants.py [name ...]
+"""
+import os, shutil, subprocess, sys, tempfile
+SRC = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MUTS = {
+ 'fstar_sign': ('(1.0 - 1.0 / (2.0 * tau_f)) * fneqm', '-(1.0 - 1.0 / (2.0 * tau_f)) * fneqm'),
+ 'kappa_sign': ('- kappa * lap', '+ kappa * lap'),
+ 'gamma_one': ('double Gamma = CS2 * (eu / CS2', 'double Gamma = CS2 * (1.0 + eu / CS2'),
+ 'drop_C_source': ('S[4] = C * (1.0 - ratio) * fs_dot;', 'S[4] = 0.0;'),
+ 'weight_diag': ('1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};', '1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 30.0};'),
+ 'FMy_ex': ('FMy += en * ey * fstar;', 'FMy += en * ex * fstar;'),
+ 'tauh_no_cpref': ('lam_f / (rho_f * cpref * CS2 * dt)', 'lam_f / (rho_f * CS2 * dt)'),
+ 'rk_coef': ('0.75 * W[q] + 0.25 * W1[q]', '0.7 * W[q] + 0.3 * W1[q]'),
+ 'no_projection': ('W[2 * n + q] *= (1.0 - Fs);', 'W[2 * n + q] *= 1.0;'),
+ 'dirichlet_ghost': ('double Tg = 2.0 * b->T_w - Tm;', 'double Tg = b->T_w;'),
+ 'wetting_sign': ('Wg[4] = m->W[4] + d', 'Wg[4] = m->W[4] - d'),
+ 'fsdot_sign': ('(solid_fraction(P, W[q], W[4 * n + q]) - Fs0[q]) / dt', '(Fs0[q] - solid_fraction(P, W[q], W[4 * n + q])) / dt'),
+ 'bulk_mu_factor': ('2.0 * beta * C * (C - 1.0)', 'beta * C * (C - 1.0)'),
+ 'side_swap': ('if (side > 0) {', 'if (side < 0) {'),
+ 'face_avg_one_side': ('avg[v] = 0.5 * (ra[v] + rb[v]);', 'avg[v] = ra[v];'),
+ 'surf_sign': ('double surf = P->surf_model == 1 ? -c->Fl * C : -C;', 'double surf = P->surf_model == 1 ? c->Fl * C : C;'),
+ 'ibm_sign_both': [('(surf * c->grad[V_MUC][0] - c->rho * u * fs_dot', '(surf * c->grad[V_MUC][0] + c->rho * u * fs_dot'),
+                   ('(surf * c->grad[V_MUC][1] - c->rho * v * fs_dot', '(surf * c->grad[V_MUC][1] + c->rho * v * fs_dot')],
+ 'ibm_sign': ('- c->rho * u * fs_dot', '+ c->rho * u * fs_dot'),
+ 'Sp_no_advect': ('S[1] = (u * drho_x + v * drho_y) * CS2 +', 'S[1] = 0.0 * (u * drho_x + v * drho_y) * CS2 +'),
+ 'SH_sign': ('S[0] = c->cp * c->val[V_T] * div_u;', 'S[0] = -c->cp * c->val[V_T] * div_u;'),
+ 'feq_quadratic': ('eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2)));\n}\n\n/* Eq. (33)', 'eu * eu / (2.0 * CS2) - uu / (2.0 * CS2)));\n}\n\n/* Eq. (33)'),
+ 'heq_drop_cpref': ('return w * cp * T * (cpref / cp + eu / CS2', 'return w * cp * T * (1.0 + eu / CS2'),
+ 'geq0_weight': ('return C - muc * Qg * (1.0 - w) / CS2;', 'return C - muc * Qg * (1.0 - 0.5 * w) / CS2;'),
+ 'recon_sign': ('out[v] = c->val[v] + rx * c->grad[v][0] + ry * c->grad[v][1];', 'out[v] = c->val[v] - rx * c->grad[v][0] + ry * c->grad[v][1];'),
+ 'recon_y_swap': ('out[v] = c->val[v] + rx * c->grad[v][0] + ry * c->grad[v][1];', 'out[v] = c->val[v] + rx * c->grad[v][0] + ry * c->grad[v][0];'),
+ 'point_rho_face': ('feq_pt[al] = feq(Q9_W[al], ex, ey, psi[V_P], rho_pt,', 'feq_pt[al] = feq(Q9_W[al], ex, ey, psi[V_P], rho_f,'),
+ 'closure_cpL': ('*T = P->T_l + (H - Hl) / cpL;', '*T = P->T_l + (H - Hl) / cpS;'),
+ 'mix_gas': ('(1.0 - Fs) * (1.0 - C) * g[2]', '(1.0 - C) * g[2]'),
+ 'wall_Fp': ('if (b->flow != OR_FLOW_OUTLET) F[1] = 0.0;', ';'),
+ 'gravity_y_sign': ('c->rho * P->gy);', '-c->rho * P->gy);'),
+ 'wall_FC': ('    F[4] = 0.0;\n    if (b->heat', '    if (b->heat'),
+ 'u_new_rho': ('double u_new = mx / (rho_f * CS2);', 'double u_new = mx / (CS2);'),
+}
+only = sys.argv[1:]
+res = {}
+for name, spec in MUTS.items():
+    pairs = spec if isinstance(spec, list) else [spec]
+    if only and name not in only: continue
+    d=os.path.join(tempfile.mkdtemp(prefix='oracle_mut_'), 'repo')
+    shutil.copytree(SRC, d, ignore=shutil.ignore_patterns('.git','_work','*.so','__pycache__','.pytest_cache','gpurun_out','_build','profiles'))
+    p=d+'/oracle/eulbfs_oracle.c'
+    s=open(p).read()
+    if any(a not in s for a, _ in pairs):
+        res[name]='PATTERN MISSING'; print(name, res[name], flush=True); continue
+    for a, b in pairs:
+        s = s.replace(a, b, 1)
+    open(p,'w').write(s)
+    subprocess.run(['gcc','-O2','-fopenmp','-ffp-contract=off','-fPIC','-shared','-o',d+'/oracle/liboracle.so',p,'-lm'],check=True)
+    r=subprocess.run([sys.executable,'-m','pytest','-q','-x','--timeout','120','tests/test_oracle_pins.py','-p','no:cacheprovider'],cwd=d,capture_output=True,text=True)
+    last=[l for l in r.stdout.splitlines() if 'FAILED' in l or 'passed' in l or 'failed' in l]
+    res[name]='caught' if r.returncode!=0 else 'SURVIVED'
+    print(name, res[name], last[:1], flush=True)
+    shutil.rmtree(os.path.dirname(d), ignore_errors=True)
+survived = {k: v for k, v in res.items() if v != 'caught'}
+print(f"{len(res) - len(survived)} of {len(res)} mutants caught; not caught: {survived}")
+sys.exit(1 if survived else 0)

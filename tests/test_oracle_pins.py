@@ -387,11 +387,12 @@ def test_enthalpy_conserved_adiabatic(oracle):
 
 def test_phase_field_conserved_no_flux(oracle):
     """Flowing two-phase state with rho_s = rho_l (no expansion source): sum C is
-    conserved to rounding through no-flux walls (R5 source vanishes)."""
+    conserved to rounding through no-flux wetting walls (the contact-angle
+    ghost cells make the face flux nonzero unless the wall face carries none)."""
     oracle.set_threads(8)
     pr = PB.Problem(nx=32, ny=32, rho=(1.0, 1.0, 0.1), mu=(0.05, 0.05, 0.005), lam=(0.4, 0.4, 0.04),
-                    sigma=0.01, walls={s: PB.Wall(heat=PB.DIRICHLET, T_w=-1.0) if s == "y-" else PB.Wall()
-                                       for s in PB.SIDES})
+                    sigma=0.01, walls={s: PB.Wall(heat=PB.DIRICHLET, T_w=-1.0, theta_deg=60.0) if s == "y-"
+                                       else PB.Wall(theta_deg=110.0) for s in PB.SIDES})
     X, Y = PB.cell_centres(pr)
     st = PB.uniform_state(pr)
     st.C = PB.droplet_profile(X, Y, 14.0, 12.0, 8.0, 4.0)
@@ -493,3 +494,67 @@ def test_ghost_ring_rules(oracle):
     H_ghost = Wg[0, g:g + 5, g - 1]
     # ghost is solid (T_g = 2 T_w - T_first < 0), so T_g = H_g / C_p,s with C = C_mirror
     assert np.allclose(0.5 * (H_ghost / 1.0 + T_first), -0.5, atol=1e-14)
+
+
+def test_hydrostatic_pressure(oracle):
+    """A liquid column at rest under gravity settles to dp/dy = rho g (the
+    gravity term of Eq. 51 and the pressure-momentum coupling of Eq. 38)."""
+    oracle.set_threads(1)
+    g = 1e-4
+    pr = PB.Problem(nx=4, ny=32, mu=(0.1, 0.1, 0.1), gy=-g, periodic_x=True,
+                    walls={"y-": PB.Wall(), "y+": PB.Wall()})
+    W, _ = oracle.run(pr, PB.uniform_state(pr, T0=0.2), 3000)
+    assert (W[1][0, 0] - W[1][-1, 0]) / (1.0 * g * 31) == pytest.approx(1.0, abs=0.03)
+
+
+def test_uniform_temperature_under_divergent_flow(oracle):
+    """Eq. (4): with T uniform, d_t H = -div(C_p T u) + C_p T div u = 0 whatever
+    the velocity field; the residual of H is only the O(dx^2) mismatch of the
+    two discrete divergences (a wrong sign of the source gives 2 C_p T div u)."""
+    pr = PB.Problem(nx=32, ny=32, periodic_x=True, periodic_y=True)
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr, T0=0.5)
+    st.u = 0.01 * np.sin(2 * np.pi * X / 32)
+    st.v = 0.005 * np.cos(2 * np.pi * Y / 32)
+    R, _, _ = oracle.residual(pr, oracle.init(pr, st))
+    scale = 0.5 * 0.01 * 2 * np.pi / 32  # C_p T max |du/dx|
+    assert np.abs(R[0]).max() < 0.02 * scale
+
+
+def test_translating_density_interface(oracle):
+    """Galilean check: a liquid slab in a gas of 1/10 its density, all moving at
+    u0, is carried at u0 (velocity error within 6 %, centroid within 0.005 cell
+    of u0 t); it pins the point density in f^eq against the face density."""
+    oracle.set_threads(8)
+    pr = PB.Problem(nx=64, ny=4, rho=(0.917, 1.0, 0.1), mu=(0.05, 0.05, 0.005), lam=(0.4, 0.4, 0.04),
+                    periodic_x=True, periodic_y=True)
+    X, _ = PB.cell_centres(pr)
+    st = PB.uniform_state(pr, T0=0.3)
+    st.C = PB.layer_profile(X, 40.0, 4.0) * PB.layer_profile(-X, -24.0, 4.0)
+    st.u[:] = 0.01
+    W0 = oracle.init(pr, st)
+    W, _ = oracle.run(pr, st, 400)
+    u = oracle.primitives(pr, W)[4]
+    assert np.abs(u - 0.01).max() < 0.06 * 0.01
+
+    def centroid(C):
+        return (C * X).sum() / C.sum()
+
+    assert abs(centroid(W[4]) - centroid(W0[4]) - 0.01 * 200) < 0.005
+
+
+def test_pressure_conserved_in_closed_box(oracle):
+    """Uniform density: the pressure equation (Eq. 38, first row) is in flux
+    form, so sum p is conserved to rounding when no mass crosses the walls,
+    whatever the flow (the quadratic terms of f^eq at a no-slip ghost would
+    otherwise leak O(u^2) through the wall faces)."""
+    oracle.set_threads(8)
+    pr = PB.Problem(nx=16, ny=16, mu=(0.02, 0.02, 0.02), walls={s: PB.Wall() for s in PB.SIDES})
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr, T0=0.2)
+    st.p[:] = 1.0
+    st.u = 0.05 * np.sin(np.pi * X / 16) * np.cos(np.pi * Y / 16)
+    st.v = -0.05 * np.cos(np.pi * X / 16) * np.sin(np.pi * Y / 16)
+    W0 = oracle.init(pr, st)
+    W, _ = oracle.step(pr, W0, np.zeros((16, 16)), 100)
+    assert abs(W[1].sum() - W0[1].sum()) <= 1e-12 * W0[1].sum()
