@@ -60,7 +60,7 @@ extern "C" {
 #define EULBFS_HEAT_DIRICHLET 1 /* cold surface at T_w                       */
 
 #define EULBFS_FP64 0 /* FP64 fields and arithmetic                                     */
-#define EULBFS_FP32 1 /* FP32 fields and flux arithmetic; H stored and accumulated in FP64 */
+#define EULBFS_FP32 1 /* FP32 flux arithmetic, p, M and dF_s/dt; H and C stored and combined in FP64 */
 
 #define EULBFS_KERNEL_FUSED 0 /* one fused flux + update kernel per RK stage      */
 #define EULBFS_KERNEL_SPLIT 1 /* ghost fill, primitives, face fluxes, update apart */

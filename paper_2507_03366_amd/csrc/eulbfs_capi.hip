@@ -153,7 +153,7 @@ Layout make_layout(const eulbfs_params* p)
     const int pitch = round_pitch(p->nx);
     L.plane_H = align_up((size_t)p->ny * pitch * 8);
     L.plane_R = align_up((size_t)p->ny * pitch * rs);
-    L.state_bytes = L.plane_H + 4 * L.plane_R;
+    L.state_bytes = 2 * L.plane_H + 3 * L.plane_R;  // H and C in double, p and M in the field type
     size_t off = 0;
     L.W0 = off;
     off += L.state_bytes;
@@ -176,13 +176,13 @@ Layout make_layout(const eulbfs_params* p)
     L.split = p->kernel == EULBFS_KERNEL_SPLIT;
     L.gpitch = round_pitch(p->nx + 2 * NG);
     L.fpitch = round_pitch(p->nx + 1);
-    L.gplane_H = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * 8);
+    L.gplane_H = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * 8);  // H and C planes
     L.gplane_R = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * rs);
     L.pstride = L.gplane_R / rs;
     L.fstride = align_up((size_t)(p->ny + 1) * L.fpitch * rs) / rs;
     if (L.split) {
         L.g = off;
-        off += L.gplane_H + 4 * L.gplane_R;
+        off += 2 * L.gplane_H + 3 * L.gplane_R;
         L.prim = off;
         off += (NPRIM + 1) * L.gplane_R;
         L.Fx = off;
@@ -196,7 +196,7 @@ Layout make_layout(const eulbfs_params* p)
 
 size_t split_scratch_bytes(const Layout& L, size_t rs)
 {
-    return L.gplane_H + 4 * L.gplane_R + (NPRIM + 1) * L.gplane_R + 10 * L.fstride * rs;
+    return 2 * L.gplane_H + 3 * L.gplane_R + (NPRIM + 1) * L.gplane_R + 10 * L.fstride * rs;
 }
 
 template <typename R>
@@ -207,7 +207,7 @@ State<R> state_at(char* base, size_t off, const Layout& L)
     s.p = (R*)(base + off + L.plane_H);
     s.mx = (R*)(base + off + L.plane_H + L.plane_R);
     s.my = (R*)(base + off + L.plane_H + 2 * L.plane_R);
-    s.C = (R*)(base + off + L.plane_H + 3 * L.plane_R);
+    s.C = (double*)(base + off + L.plane_H + 3 * L.plane_R);
     return s;
 }
 
@@ -219,7 +219,7 @@ SplitScratch<R> split_at(char* base, const Layout& L)
     X.g.p = (R*)(base + L.g + L.gplane_H);
     X.g.mx = (R*)(base + L.g + L.gplane_H + L.gplane_R);
     X.g.my = (R*)(base + L.g + L.gplane_H + 2 * L.gplane_R);
-    X.g.C = (R*)(base + L.g + L.gplane_H + 3 * L.gplane_R);
+    X.g.C = (double*)(base + L.g + L.gplane_H + 3 * L.gplane_R);
     X.gpitch = L.gpitch;
     X.prim = (R*)(base + L.prim);
     X.pstride = L.pstride;
@@ -397,7 +397,7 @@ int do_residual(eulbfs_solver* h, double* Rout, double* Fx, double* Fy, int on_d
     } else {
         Layout L2 = L;
         L2.g = 0;
-        L2.prim = L2.g + L.gplane_H + 4 * L.gplane_R;
+        L2.prim = L2.g + 2 * L.gplane_H + 3 * L.gplane_R;
         L2.Fx = L2.prim + (NPRIM + 1) * L.gplane_R;
         L2.Fy = L2.Fx + 5 * L.fstride * rs;
         X = split_at<R>(tmp, L2);

@@ -1,10 +1,13 @@
 // Device-side building blocks of the EULBFS time step for gfx950.
 //
 // Everything here is templated on the field/arithmetic type R (double or
-// float).  The total enthalpy H is always stored and combined in double, and
-// the closure H -> (T, F_l) of Eqs. (5)-(6) always runs in double: in FP32
-// mode the enthalpy increments per step are far below the float spacing of
-// H ~ L near the melting point.
+// float).  Two fields are always stored and combined in double: the total
+// enthalpy H, whose closure H -> (T, F_l) of Eqs. (5)-(6) also runs in double
+// (in FP32 mode the enthalpy increments per step are far below the float
+// spacing of H ~ L near the melting point), and the order parameter C, whose
+// chemical potential 2 beta C(C-1)(2C-1) - kappa lap C is a difference of two
+// nearly equal terms across the diffuse interface (a float C puts a noise of
+// ~1e-8 on the capillary force that drives p and u).
 //
 // Storage: structure of arrays.  Each conserved field is one plane of
 // ny rows of `pitch` elements (pitch >= nx, a multiple of 64), x fastest.
@@ -51,17 +54,31 @@ struct State {
     R* p;
     R* mx;
     R* my;
-    R* C;
+    double* C;
 };
 
 template <typename R>
 struct Cons {
     double H;
-    R p, mx, my, C;
+    R p, mx, my;
+    double C;
 };
 
 __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
 __device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (within an ulp or two of the correctly rounded value for the positive,
+// normal operands used here: densities, heat capacities, enthalpy ranges).
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Eq. (7): gamma = F_s g_s + (1 - F_s) C g_l + (1 - F_s)(1 - C) g_g.
 template <typename R>
@@ -82,13 +99,13 @@ __device__ __forceinline__ void closure(const DevParams& P, double H, double Cc,
     const double Hl = cpL * P.T_l + P.latent;
     if (H < Hs) {
         Fl = 0.0;
-        T = P.T_s + (H - Hs) / cpS;
+        T = P.T_s + (H - Hs) * rcp(cpS);
     } else if (H > Hl) {
         Fl = 1.0;
-        T = P.T_l + (H - Hl) / cpL;
+        T = P.T_l + (H - Hl) * rcp(cpL);
     } else {
         const double d = Hl - Hs;
-        Fl = d > 1e-300 ? (H - Hs) / d : 1.0;
+        Fl = d > 1e-300 ? (H - Hs) * rcp(d) : 1.0;
         T = P.T_s + Fl * (P.T_l - P.T_s);
     }
 }
@@ -143,7 +160,7 @@ __device__ __forceinline__ Cons<R> read_cell(const State<R>& S, int pitch, int i
 // Wall rule for ghost layer k (1..3) of `side` (0 x-, 1 x+, 2 y-, 3 y+):
 // m is the mirrored interior cell, Cw the C of the first interior cell.
 template <typename R>
-__device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int k, const Cons<R>& m, R Cw)
+__device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int k, const Cons<R>& m, double Cw)
 {
     Cons<R> g;
     g.p = m.p;
@@ -155,12 +172,12 @@ __device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int 
     const R gt = f == FLOW_NOSLIP ? -mt : mt;
     g.mx = xside ? gn : gt;
     g.my = xside ? gt : gn;
-    g.C = m.C + R((2 * k - 1) * P.wet[side]) * Cw * (R(1) - Cw);
+    g.C = m.C + ((2 * k - 1) * P.wet[side]) * Cw * (1.0 - Cw);
     if (P.heat[side] == HEAT_DIRICHLET) {
         double Fl, Tm;
-        closure(P, m.H, clamp01((double)m.C), Fl, Tm);
+        closure(P, m.H, clamp01(m.C), Fl, Tm);
         const double Tg = 2.0 * P.T_w[side] - Tm;
-        g.H = ghost_enthalpy(P, Tg, (double)g.C);
+        g.H = ghost_enthalpy(P, Tg, g.C);
     } else {
         g.H = m.H;
     }
@@ -187,7 +204,7 @@ __device__ __forceinline__ Cons<R> load_x(const DevParams& P, const State<R>& S,
         side = 1; k = i - P.nx + 1; m = P.nx - k; first = P.nx - 1;
     }
     const Cons<R> wm = read_cell(S, P.pitch, m, j);
-    const R Cw = S.C[(size_t)j * P.pitch + first];
+    const double Cw = S.C[(size_t)j * P.pitch + first];
     return wall_ghost(P, side, k, wm, Cw);
 }
 
@@ -210,7 +227,7 @@ __device__ __forceinline__ Cons<R> load_bc(const DevParams& P, const State<R>& S
         side = 3; k = j - P.ny + 1; m = P.ny - k; first = P.ny - 1;
     }
     const Cons<R> wm = load_x(P, S, i, m);
-    const R Cw = load_x(P, S, i, first).C;
+    const double Cw = load_x(P, S, i, first).C;
     return wall_ghost(P, side, k, wm, Cw);
 }
 
@@ -221,14 +238,14 @@ enum { VT = 0, VC, VFS, VU, VV, VP, VMU, NPRIM };  // + rho stored after
 template <typename R>
 __device__ __forceinline__ void primitives(const DevParams& P, const Cons<R>& w, R out[NPRIM + 1])
 {
-    const double Cc = clamp01((double)w.C);
+    const double Cc = clamp01(w.C);
     double Fl, T;
     closure(P, w.H, Cc, Fl, T);
     const R Fs = R(Cc * (1.0 - Fl));
     const R rho = mix<R>(P.rho, R(Cc), Fs);
-    const R inv = R(3) / rho;  // 1 / (rho c_s^2)
+    const R inv = R(3) * rcp(rho);  // 1 / (rho c_s^2)
     out[VT] = R(T);
-    out[VC] = w.C;
+    out[VC] = R(w.C);
     out[VFS] = Fs;
     out[VU] = w.mx * inv;
     out[VV] = w.my * inv;
@@ -237,12 +254,13 @@ __device__ __forceinline__ void primitives(const DevParams& P, const Cons<R>& w,
     out[NPRIM] = rho;
 }
 
-// Chemical potential (Sec. 2.3.1): 2 beta C (C-1)(2C-1) - kappa lap C.
-template <typename R>
-__device__ __forceinline__ R chem_potential(const DevParams& P, R C, R cE, R cW, R cN, R cS)
+// Chemical potential (Sec. 2.3.1): 2 beta C (C-1)(2C-1) - kappa lap C, in
+// double whatever the field type.
+__device__ __forceinline__ double chem_potential(const DevParams& P, double C, double cE, double cW, double cN,
+                                                 double cS)
 {
-    const R lap = (cE + cW + cN + cS - R(4) * C) * R(P.inv_dx2);
-    return R(2 * P.beta) * C * (C - R(1)) * (R(2) * C - R(1)) - R(P.kappa) * lap;
+    const double lap = (cE + cW + cN + cS - 4.0 * C) * P.inv_dx2;
+    return 2.0 * P.beta * C * (C - 1.0) * (2.0 * C - 1.0) - P.kappa * lap;
 }
 
 // ---------------------------------------------------------------------------
@@ -250,113 +268,128 @@ __device__ __forceinline__ R chem_potential(const DevParams& P, R C, R cE, R cW,
 //
 // Local frame: n is the face normal (from cell a to cell b), t the tangent.
 // The D2Q9 set maps onto itself under the x <-> y reflection, so one routine
-// serves both orientations: it takes velocities (u_n, u_t) and gradients
-// (d/dn, d/dt) and returns (F_H, F_p, F_Mn, F_Mt, F_C) with F_Mn = sum e_n e_n f*,
-// F_Mt = sum e_n e_t f*.
+// serves both orientations: it returns (F_H, F_p, F_Mn, F_Mt, F_C) with
+// F_Mn = sum e_n e_n f*, F_Mt = sum e_n e_t f*.
 //
-// Surrounding points x_f - e delta_t (Eq. 54): e_n > 0 lies in cell a,
-// e_n < 0 in cell b, e_n = 0 on the face (average of both extrapolations).
-// With a_X = tau_X - 1/2 the star distribution is
-//   X* = (1 - a_X) X^eq(x_f) + a_X X^eq(x_f - e delta_t)
-// so each flux is (1 - a_X) times a moment of the face equilibrium (known in
-// closed form from Eqs. 11, 29, 42) plus a_X times the same moment of the
-// point equilibria.
+// Surrounding points x_f - e delta_t (Eq. 54): e_n = +1 lies in cell a,
+// e_n = -1 in cell b, e_n = 0 on the face (average of both extrapolations).
+// Every reconstructed value at a point is base - e_t d, with per variable
+//   A = psi_a + (dx/2 - delta_t) dpsi_a/dn        (group e_n = +1)
+//   B = psi_b - (dx/2 - delta_t) dpsi_b/dn        (group e_n = -1)
+//   M = average of both extrapolations to x_f     (group e_n = 0; also the
+//                                                  old-level face value)
+//   d = delta_t dpsi/dt of the group's cell (the mean for the face group).
+// With a_X = tau_X - 1/2 each star distribution is
+//   X* = (1 - a_X) X^eq(x_f) + a_X X^eq(x_f - e delta_t),
+// so each flux is (1 - a_X) times a moment of the face equilibrium (closed
+// form from Eqs. 11, 29, 42) plus a_X times the same moment of the point
+// equilibria.  In those point moments every term that is linear in the
+// reconstructed values sums in closed form over the nine points (the
+// offsets +-d cancel); only the products rho q, C_p T q and C e.u, with
+//   q = e.u/c_s^2 + (e.u)^2/(2 c_s^4) - u^2/(2 c_s^2),
+// are evaluated point by point.
 // ---------------------------------------------------------------------------
-template <typename R, int LAT>
-__device__ __forceinline__ void face_flux(const DevParams& P, const R va[NPRIM], const R gna[NPRIM],
-                                          const R gta[NPRIM], const R vb[NPRIM], const R gnb[NPRIM],
-                                          const R gtb[NPRIM], R F[5])
-{
-    const R h = R(0.5 * P.dx);
-    const R ds = R(P.delta_t);
-    const R sh = R(0.5 * P.dx - P.delta_t);
+template <typename R>
+struct Bases {
     R A[NPRIM], B[NPRIM], M[NPRIM], da[NPRIM], db[NPRIM], dm[NPRIM];
-#pragma unroll
-    for (int k = 0; k < NPRIM; ++k) {
-        A[k] = va[k] + sh * gna[k];
-        B[k] = vb[k] - sh * gnb[k];
-        M[k] = R(0.5) * ((va[k] + h * gna[k]) + (vb[k] - h * gnb[k]));
-        da[k] = ds * gta[k];
-        db[k] = ds * gtb[k];
-        dm[k] = R(0.5) * (da[k] + db[k]);
-    }
+};
+
+// Bases of one variable from a plane of cell values: a and b are the two
+// cells (b = a + sn), sn the stride along n, st the stride along t.
+template <typename R>
+__device__ __forceinline__ void face_bases(const R* v, int a, int sn, int st, R c_sh, R c_h, R c_ds, R& A, R& B,
+                                           R& M, R& da, R& db, R& dm)
+{
+    const int b = a + sn;
+    const R va = v[a], vb = v[b];
+    const R ga = v[b] - v[a - sn];  // 2 dx dpsi_a/dn
+    const R gb = v[b + sn] - va;    // 2 dx dpsi_b/dn
+    A = va + c_sh * ga;
+    B = vb - c_sh * gb;
+    M = R(0.5) * ((va + c_h * ga) + (vb - c_h * gb));
+    da = c_ds * (v[a + st] - v[a - st]);
+    db = c_ds * (v[b + st] - v[b - st]);
+    dm = R(0.5) * (da + db);
+}
+
+template <typename R, int LAT>
+__device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X, R F[5])
+{
     // old-level face state (text after Eq. 54) -> Eq. (7)
-    const R Cf = clamp01(M[VC]);
-    const R Fsf = clamp01(M[VFS]);
+    const R Cf = clamp01(X.M[VC]);
+    const R Fsf = clamp01(X.M[VFS]);
     const R rho_f = mix<R>(P.rho, Cf, Fsf);
     const R mu_f = mix<R>(P.mu, Cf, Fsf);
     const R lam_f = mix<R>(P.lam, Cf, Fsf);
     const R cp_f = mix<R>(P.cp, Cf, Fsf);
-    const R cpref = R(P.cpref);
-    const R Q = R(P.muQ);
 
-    R p_f = 0, m_n = 0, m_t = 0, C_new = 0, SH = 0, SG = 0, SMn = 0, SMt = 0;
+    // point sums: group 0: e_n = +1, group 1: e_n = -1, group 2: e_n = 0
+    R G[3] = {0, 0, 0}, Gt[3] = {0, 0, 0};  // sum w rho q, sum e_t w rho q
+    R Qs[2] = {0, 0}, Qt[2] = {0, 0};       // sum w q, sum e_t w q      (e_n != 0)
+    R Hq[2] = {0, 0};                       // sum wh C_p T q            (e_n != 0)
+    R Ce[3] = {0, 0, 0};                    // sum wh C e.u
 #pragma unroll
-    for (int pn = 0; pn < 3; ++pn) {
-        const int en = pn == 0 ? 1 : (pn == 1 ? -1 : 0);
-        const R* base = pn == 0 ? A : (pn == 1 ? B : M);
-        const R* dd = pn == 0 ? da : (pn == 1 ? db : dm);
+    for (int g = 0; g < 3; ++g) {
+        const int en = g == 0 ? 1 : (g == 1 ? -1 : 0);
+        const R* base = g == 0 ? X.A : (g == 1 ? X.B : X.M);
+        const R* dd = g == 0 ? X.da : (g == 1 ? X.db : X.dm);
 #pragma unroll
-        for (int pt = 0; pt < 3; ++pt) {
-            const int et = pt == 0 ? 0 : (pt == 1 ? 1 : -1);
+        for (int k = 0; k < 3; ++k) {
+            const int et = k == 0 ? 0 : (k == 1 ? 1 : -1);
             const R w9 = en == 0 ? (et == 0 ? R(4.0 / 9.0) : R(1.0 / 9.0)) : (et == 0 ? R(1.0 / 9.0) : R(1.0 / 36.0));
             const bool in_hg = LAT == 9 || en == 0 || et == 0;
             const R wh = LAT == 9 ? w9 : (en == 0 && et == 0 ? R(1.0 / 3.0) : R(1.0 / 6.0));
-            // point values (Eq. 54): base - e_t * delta_t * d/dt
             const R C = base[VC] - R(et) * dd[VC];
             const R Fs = base[VFS] - R(et) * dd[VFS];
             const R un = base[VU] - R(et) * dd[VU];
             const R ut = base[VV] - R(et) * dd[VV];
-            const R p = base[VP] - R(et) * dd[VP];
             const R Cc = clamp01(C);
             const R Fsc = clamp01(Fs);
-            const R rho_pt = mix<R>(P.rho, Cc, Fsc);
+            const R rho = mix<R>(P.rho, Cc, Fsc);
             const R eu = R(en) * un + R(et) * ut;
             const R uu = un * un + ut * ut;
-            // e.u/c_s^2 + (e.u)^2/(2 c_s^4) - u^2/(2 c_s^2) with c_s^2 = 1/3
             const R q = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-            // Eq. (29) at the point and Eq. (33) with the face density
-            const R feq = w9 * p + (w9 / R(3)) * rho_pt * q;
-            p_f += feq;
-            if (en != 0) m_n += R(en) * feq;
-            if (et != 0) m_t += R(et) * feq;
+            const R rq = rho * q;
+            G[g] += w9 * rq;
+            if (et != 0) Gt[g] += R(et) * w9 * rq;
             if (en != 0) {
-                const R feqm = w9 * p + (w9 / R(3)) * rho_f * q;
-                SMn += feqm;
-                if (et != 0) SMt += R(en * et) * feqm;
+                Qs[g] += w9 * q;
+                if (et != 0) Qt[g] += R(et) * w9 * q;
             }
             if (in_hg) {
-                const R mu = base[VMU] - R(et) * dd[VMU];
-                // Eq. (42)
-                R geq;
-                if (en == 0 && et == 0)
-                    geq = C - R(3) * mu * Q * (R(1) - wh);
-                else
-                    geq = R(3) * wh * (mu * Q + C * eu);
-                C_new += geq;
+                if (en != 0 || et != 0) Ce[g] += wh * C * eu;
                 if (en != 0) {
-                    SG += R(en) * geq;
-                    // Eq. (9), alpha != 0
                     const R T = base[VT] - R(et) * dd[VT];
-                    const R cp_pt = mix<R>(P.cp, Cc, Fsc);
-                    const R heq = wh * (cpref * T + cp_pt * T * q);
-                    SH += R(en) * heq;
+                    const R cp = mix<R>(P.cp, Cc, Fsc);
+                    Hq[g] += wh * cp * T * q;
                 }
             }
         }
     }
-    // Eq. (56): new face state; equilibria at the face have closed-form moments
-    const R inv_rho = R(1) / rho_f;
+    const R sixth = R(1.0 / 6.0), third = R(1.0 / 3.0);
+    // Eq. (56): new face state from the point equilibria f^eq (Eq. 29) and g^eq (Eq. 42)
+    const R p_f = sixth * (X.A[VP] + X.B[VP]) + R(2.0 / 3.0) * X.M[VP] + third * (G[0] + G[1] + G[2]);
+    const R m_n = sixth * (X.A[VP] - X.B[VP]) + third * (G[0] - G[1]);
+    const R m_t = -R(1.0 / 18.0) * (X.da[VP] + X.db[VP]) - R(2.0 / 9.0) * X.dm[VP] + third * (Gt[0] + Gt[1] + Gt[2]);
+    const R Q = R(P.muQ);
+    const R C_new = X.M[VC] + R(3) * Q * (sixth * (X.A[VMU] + X.B[VMU]) - third * X.M[VMU]) +
+                    R(3) * (Ce[0] + Ce[1] + Ce[2]);
+    // point moments of the star distributions (f^eq-m with the face density, Eq. 33)
+    const R SMn = sixth * (X.A[VP] + X.B[VP]) + third * rho_f * (Qs[0] + Qs[1]);
+    const R SMt = R(1.0 / 18.0) * (X.db[VP] - X.da[VP]) + third * rho_f * (Qt[0] - Qt[1]);
+    const R SH = R(P.cpref) * sixth * (X.A[VT] - X.B[VT]) + (Hq[0] - Hq[1]);
+    const R SG = R(3) * Q * sixth * (X.A[VMU] - X.B[VMU]) + R(3) * (Ce[0] - Ce[1]);
+
+    const R inv_rho = rcp(rho_f);
     const R un_f = R(3) * m_n * inv_rho;
     const R ut_f = R(3) * m_t * inv_rho;
     const R a_h = R(P.k_h) * lam_f * inv_rho;
     const R a_f = R(P.k_f) * mu_f * inv_rho;
     const R a_g = R(P.a_g);
-    const R T_f = M[VT];
-    F[0] = (R(1) - a_h) * cp_f * T_f * un_f + a_h * SH;
+    F[0] = (R(1) - a_h) * cp_f * X.M[VT] * un_f + a_h * SH;
     F[1] = m_n;
-    F[2] = (R(1) - a_f) * (p_f + rho_f * un_f * un_f) * R(1.0 / 3.0) + a_f * SMn;
-    F[3] = (R(1) - a_f) * rho_f * un_f * ut_f * R(1.0 / 3.0) + a_f * SMt;
+    F[2] = (R(1) - a_f) * (p_f + rho_f * un_f * un_f) * third + a_f * SMn;
+    F[3] = (R(1) - a_f) * rho_f * un_f * ut_f * third + a_f * SMt;
     F[4] = (R(1) - a_g) * C_new * un_f + a_g * SG;
 }
 

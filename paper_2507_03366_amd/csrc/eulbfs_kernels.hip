@@ -31,7 +31,7 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     R Fl = R(0);
     if (P.surf_model == 1) {
         double fl, T;
-        closure(P, Wk.H, clamp01((double)Wk.C), fl, T);
+        closure(P, Wk.H, clamp01(Wk.C), fl, T);
         Fl = R(fl);
     }
     const R fsd = fsdot[q];
@@ -53,9 +53,9 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     const R pnew = ca * wn.p + cb * Wk.p + cdtr * res[1];
     R mxnew = ca * wn.mx + cb * Wk.mx + cdtr * res[2];
     R mynew = ca * wn.my + cb * Wk.my + cdtr * res[3];
-    const R Cnew = ca * wn.C + cb * Wk.C + cdtr * res[4];
+    const double Cnew = K.ca * wn.C + K.cb * Wk.C + cdt * (double)res[4];
     // rigid solid: M <- (1 - F_s) M with F_s of the new stage value
-    const double Fs_new = solid_fraction(P, Hnew, (double)Cnew);
+    const double Fs_new = solid_fraction(P, Hnew, Cnew);
     mxnew *= R(1.0 - Fs_new);
     mynew *= R(1.0 - Fs_new);
     out.H[q] = Hnew;
@@ -63,24 +63,39 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     out.mx[q] = mxnew;
     out.my[q] = mynew;
     out.C[q] = Cnew;
-    if (K.last) fsdot[q] = R((Fs_new - solid_fraction(P, wn.H, (double)wn.C)) * P.inv_dt);
+    if (K.last) fsdot[q] = R((Fs_new - solid_fraction(P, wn.H, wn.C)) * P.inv_dt);
 }
 
 // ---------------------------------------------------------------------------
 // Fused stage kernel.
+//
+// LDS: the W tile with three halo layers is only needed until the primitive
+// fields exist, so the face fluxes reuse its bytes; the primitive planes
+// (tile + two halo layers) live through the whole stage.
 // ---------------------------------------------------------------------------
+template <typename R, int TX, int TY>
+struct FusedLds {
+    static constexpr int W3 = TX + 2 * NG, H3 = TY + 2 * NG;
+    static constexpr int W2 = TX + 4, H2 = TY + 4;
+    static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+    static constexpr size_t BYTES_W = (size_t)W3 * H3 * (2 * sizeof(double) + 3 * sizeof(R));
+    static constexpr size_t BYTES_F = (size_t)5 * (NFX + NFY) * sizeof(R);
+    static constexpr size_t BYTES_U = BYTES_W > BYTES_F ? BYTES_W : BYTES_F;
+};
+
 template <typename R, int LAT, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_fused(DevParams P, StageCoef K, State<R> in, State<R> Wn, State<R> out, R* fsdot)
 {
+    using L = FusedLds<R, TX, TY>;
     constexpr int NT = TX * TY;
-    constexpr int W3 = TX + 2 * NG, H3 = TY + 2 * NG;
-    constexpr int W2 = TX + 4, H2 = TY + 4;
-    constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
-    __shared__ double sH[W3 * H3];
-    __shared__ R sW[4][W3 * H3];
+    constexpr int W3 = L::W3, H3 = L::H3, W2 = L::W2, H2 = L::H2, NFX = L::NFX, NFY = L::NFY;
+    __shared__ __align__(16) char sU[L::BYTES_U];
     __shared__ R sP[NPRIM + 1][W2 * H2];
-    __shared__ R sF[5][NFX + NFY];
+    double* sH = reinterpret_cast<double*>(sU);                                // H, then C
+    double* sC = sH + W3 * H3;
+    R* sW = reinterpret_cast<R*>(sU + (size_t)2 * W3 * H3 * sizeof(double));  // p, Mx, My
+    R* sF = reinterpret_cast<R*>(sU);                                          // 5 planes of NFX+NFY
 
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
@@ -90,10 +105,10 @@ __global__ void __launch_bounds__(TX* TY)
         const int li = q % W3, lj = q / W3;
         const Cons<R> w = load_bc(P, in, i0 + li - NG, j0 + lj - NG);
         sH[q] = w.H;
-        sW[0][q] = w.p;
-        sW[1][q] = w.mx;
-        sW[2][q] = w.my;
-        sW[3][q] = w.C;
+        sW[0 * W3 * H3 + q] = w.p;
+        sW[1 * W3 * H3 + q] = w.mx;
+        sW[2 * W3 * H3 + q] = w.my;
+        sC[q] = w.C;
     }
     __syncthreads();
 
@@ -103,70 +118,59 @@ __global__ void __launch_bounds__(TX* TY)
         const int q3 = (lj + 1) * W3 + li + 1;
         Cons<R> w;
         w.H = sH[q3];
-        w.p = sW[0][q3];
-        w.mx = sW[1][q3];
-        w.my = sW[2][q3];
-        w.C = sW[3][q3];
+        w.p = sW[q3];
+        w.mx = sW[W3 * H3 + q3];
+        w.my = sW[2 * W3 * H3 + q3];
+        w.C = sC[q3];
         R pr[NPRIM + 1];
         primitives(P, w, pr);
-        pr[VMU] = chem_potential(P, w.C, sW[3][q3 + 1], sW[3][q3 - 1], sW[3][q3 + W3], sW[3][q3 - W3]);
+        pr[VMU] = R(chem_potential(P, w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3], sC[q3 - W3]));
 #pragma unroll
         for (int k = 0; k <= NPRIM; ++k) sP[k][q] = pr[k];
     }
     __syncthreads();
 
-    // 3. every face of the tile once
+    // 3. every face of the tile once (fluxes overwrite the dead W tile)
     const R i2dx = R(P.inv_2dx);
-    for (int f = tid; f < NFX + NFY; f += NT) {
-        R va[NPRIM], gna[NPRIM], gta[NPRIM], vb[NPRIM], gnb[NPRIM], gtb[NPRIM], F[5];
+    const R c_sh = R(0.5 * P.dx - P.delta_t) * i2dx, c_h = R(0.5 * P.dx) * i2dx, c_ds = R(P.delta_t) * i2dx;
+    constexpr int NF = NFX + NFY;
+    for (int f = tid; f < NF; f += NT) {
+        Bases<R> X;
+        R F[5];
         if (f < NFX) {
             const int fi = f % (TX + 1), fj = f / (TX + 1);
-            const int a = (fj + 2) * W2 + fi + 1, b = a + 1;
+            const int a = (fj + 2) * W2 + fi + 1;
 #pragma unroll
-            for (int k = 0; k < NPRIM; ++k) {
-                va[k] = sP[k][a];
-                gna[k] = (sP[k][a + 1] - sP[k][a - 1]) * i2dx;
-                gta[k] = (sP[k][a + W2] - sP[k][a - W2]) * i2dx;
-                vb[k] = sP[k][b];
-                gnb[k] = (sP[k][b + 1] - sP[k][b - 1]) * i2dx;
-                gtb[k] = (sP[k][b + W2] - sP[k][b - W2]) * i2dx;
-            }
-            face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+            for (int k = 0; k < NPRIM; ++k)
+                face_bases(sP[k], a, 1, W2, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k], X.dm[k]);
+            face_flux<R, LAT>(P, X, F);
             const int gi = i0 + fi;
             if (!P.periodic_x) {
                 if (gi == 0) wall_face(P, 0, F);
                 else if (gi == P.nx) wall_face(P, 1, F);
             }
-            sF[0][f] = F[0];
-            sF[1][f] = F[1];
-            sF[2][f] = F[2];
-            sF[3][f] = F[3];
-            sF[4][f] = F[4];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sF[k * NF + f] = F[k];
         } else {
             const int g = f - NFX;
             const int fi = g % TX, fj = g / TX;
-            const int a = (fj + 1) * W2 + fi + 2, b = a + W2;
+            const int a = (fj + 1) * W2 + fi + 2;
 #pragma unroll
             for (int k = 0; k < NPRIM; ++k) {
                 const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
-                va[k] = sP[ks][a];
-                gna[k] = (sP[ks][a + W2] - sP[ks][a - W2]) * i2dx;
-                gta[k] = (sP[ks][a + 1] - sP[ks][a - 1]) * i2dx;
-                vb[k] = sP[ks][b];
-                gnb[k] = (sP[ks][b + W2] - sP[ks][b - W2]) * i2dx;
-                gtb[k] = (sP[ks][b + 1] - sP[ks][b - 1]) * i2dx;
+                face_bases(sP[ks], a, W2, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k], X.dm[k]);
             }
-            face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+            face_flux<R, LAT>(P, X, F);
             const int gj = j0 + fj;
             if (!P.periodic_y) {
                 if (gj == 0) wall_face(P, 2, F);
                 else if (gj == P.ny) wall_face(P, 3, F);
             }
-            sF[0][f] = F[0];
-            sF[1][f] = F[1];
-            sF[2][f] = F[3];  // x-momentum flux through a y-face: sum e_y e_x f*
-            sF[3][f] = F[2];
-            sF[4][f] = F[4];
+            sF[0 * NF + f] = F[0];
+            sF[1 * NF + f] = F[1];
+            sF[2 * NF + f] = F[3];  // x-momentum flux through a y-face: sum e_y e_x f*
+            sF[3 * NF + f] = F[2];
+            sF[4 * NF + f] = F[4];
         }
     }
     __syncthreads();
@@ -180,7 +184,8 @@ __global__ void __launch_bounds__(TX* TY)
     const R idx = R(1.0 / P.dx);
     R dF[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) dF[k] = (sF[k][fl + 1] - sF[k][fl]) * idx + (sF[k][fb + TX] - sF[k][fb]) * idx;
+    for (int k = 0; k < 5; ++k)
+        dF[k] = (sF[k * NF + fl + 1] - sF[k * NF + fl]) * idx + (sF[k * NF + fb + TX] - sF[k * NF + fb]) * idx;
     const int c2 = (ty + 2) * W2 + tx + 2;
     R c[NPRIM + 1];
 #pragma unroll
@@ -191,14 +196,8 @@ __global__ void __launch_bounds__(TX* TY)
     const R dry = (sP[NPRIM][c2 + W2] - sP[NPRIM][c2 - W2]) * i2dx;
     const R dmx = (sP[VMU][c2 + 1] - sP[VMU][c2 - 1]) * i2dx;
     const R dmy = (sP[VMU][c2 + W2] - sP[VMU][c2 - W2]) * i2dx;
-    const int c3 = (ty + NG) * W3 + tx + NG;
-    Cons<R> wk;
-    wk.H = sH[c3];
-    wk.p = sW[0][c3];
-    wk.mx = sW[1][c3];
-    wk.my = sW[2][c3];
-    wk.C = sW[3][c3];
     const size_t q = (size_t)j * P.pitch + i;
+    const Cons<R> wk = read_cell(in, P.pitch, i, j);
     cell_update(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, (R*)nullptr, 0, q);
 }
 
@@ -236,7 +235,7 @@ __global__ void k_split_prims(DevParams P, State<R> g, int gpitch, R* prim, size
     w.C = g.C[q];
     R pr[NPRIM + 1];
     primitives(P, w, pr);
-    pr[VMU] = chem_potential(P, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]);
+    pr[VMU] = R(chem_potential(P, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]));
 #pragma unroll
     for (int k = 0; k <= NPRIM; ++k) prim[k * pstride + q] = pr[k];
 }
@@ -248,20 +247,16 @@ __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gp
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const R i2dx = R(P.inv_2dx);
-    R va[NPRIM], gna[NPRIM], gta[NPRIM], vb[NPRIM], gnb[NPRIM], gtb[NPRIM], F[5];
+    const R c_sh = R(0.5 * P.dx - P.delta_t) * i2dx, c_h = R(0.5 * P.dx) * i2dx, c_ds = R(P.delta_t) * i2dx;
+    Bases<R> X;
+    R F[5];
     if (i <= P.nx && j < P.ny) {  // x-face i between cells i-1 and i
-        const size_t a = (size_t)(j + NG) * gpitch + (i - 1 + NG), b = a + 1;
+        const int a = (j + NG) * gpitch + (i - 1 + NG);
 #pragma unroll
-        for (int k = 0; k < NPRIM; ++k) {
-            const R* pk = prim + k * pstride;
-            va[k] = pk[a];
-            gna[k] = (pk[a + 1] - pk[a - 1]) * i2dx;
-            gta[k] = (pk[a + gpitch] - pk[a - gpitch]) * i2dx;
-            vb[k] = pk[b];
-            gnb[k] = (pk[b + 1] - pk[b - 1]) * i2dx;
-            gtb[k] = (pk[b + gpitch] - pk[b - gpitch]) * i2dx;
-        }
-        face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+        for (int k = 0; k < NPRIM; ++k)
+            face_bases(prim + k * pstride, a, 1, gpitch, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
+                       X.dm[k]);
+        face_flux<R, LAT>(P, X, F);
         if (!P.periodic_x) {
             if (i == 0) wall_face(P, 0, F);
             else if (i == P.nx) wall_face(P, 1, F);
@@ -271,19 +266,14 @@ __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gp
         for (int k = 0; k < 5; ++k) Fx[k * fstride + o] = F[k];
     }
     if (i < P.nx && j <= P.ny) {  // y-face j between cells j-1 and j
-        const size_t a = (size_t)(j - 1 + NG) * gpitch + (i + NG), b = a + gpitch;
+        const int a = (j - 1 + NG) * gpitch + (i + NG);
 #pragma unroll
         for (int k = 0; k < NPRIM; ++k) {
             const int ks = k == VU ? VV : (k == VV ? VU : k);
-            const R* pk = prim + ks * pstride;
-            va[k] = pk[a];
-            gna[k] = (pk[a + gpitch] - pk[a - gpitch]) * i2dx;
-            gta[k] = (pk[a + 1] - pk[a - 1]) * i2dx;
-            vb[k] = pk[b];
-            gnb[k] = (pk[b + gpitch] - pk[b - gpitch]) * i2dx;
-            gtb[k] = (pk[b + 1] - pk[b - 1]) * i2dx;
+            face_bases(prim + ks * pstride, a, gpitch, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
+                       X.dm[k]);
         }
-        face_flux<R, LAT>(P, va, gna, gta, vb, gnb, gtb, F);
+        face_flux<R, LAT>(P, X, F);
         if (!P.periodic_y) {
             if (j == 0) wall_face(P, 2, F);
             else if (j == P.ny) wall_face(P, 3, F);
@@ -353,7 +343,7 @@ __global__ void k_init(DevParams P, const double* prim6, State<R> out, R* fsdot)
     out.p[q] = R(p);
     out.mx[q] = R(rho / 3.0 * u);
     out.my[q] = R(rho / 3.0 * v);
-    out.C[q] = R(C);
+    out.C[q] = C;
     fsdot[q] = R(0);
 }
 
@@ -374,7 +364,7 @@ __global__ void k_set_conserved(DevParams P, const double* w6, State<R> out, R* 
             case 1: out.p[q] = R(x); break;
             case 2: out.mx[q] = R(x); break;
             case 3: out.my[q] = R(x); break;
-            case 4: out.C[q] = R(x); break;
+            case 4: out.C[q] = x; break;
             default: fsdot[q] = R(x); break;
         }
     }
@@ -399,11 +389,11 @@ __global__ void k_export(DevParams P, State<R> S, const R* fsdot, int what, doub
             default: x = fsdot[q]; break;
         }
     } else if (what == 12) {
-        const R cE = load_bc(P, S, i + 1, j).C, cW = load_bc(P, S, i - 1, j).C;
-        const R cN = load_bc(P, S, i, j + 1).C, cS = load_bc(P, S, i, j - 1).C;
+        const double cE = load_bc(P, S, i + 1, j).C, cW = load_bc(P, S, i - 1, j).C;
+        const double cN = load_bc(P, S, i, j + 1).C, cS = load_bc(P, S, i, j - 1).C;
         x = chem_potential(P, w.C, cE, cW, cN, cS);
     } else {
-        const double Cc = clamp01((double)w.C);
+        const double Cc = clamp01(w.C);
         double Fl, T;
         closure(P, w.H, Cc, Fl, T);
         const double Fs = Cc * (1.0 - Fl);
@@ -465,19 +455,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(DevParams P, Sta
     for (size_t s = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; s < n; s += (size_t)gridDim.x * RED_THREADS) {
         const int i = (int)(s % P.nx), j = (int)(s / P.nx);
         const Cons<R> w = read_cell(S, P.pitch, i, j);
-        const double Cc = clamp01((double)w.C);
+        const double Cc = clamp01(w.C);
         double Fl, T;
         closure(P, w.H, Cc, Fl, T);
         const double Fs = Cc * (1.0 - Fl);
         const double rho = mix<double>(P.rho, Cc, Fs);
         const double u = 3.0 * (double)w.mx / rho, v = 3.0 * (double)w.my / rho;
         acc[0] += rho;
-        acc[1] += (double)w.C;
+        acc[1] += w.C;
         acc[2] += w.H;
         acc[3] += Fs;
         acc[4] = fmax(acc[4], sqrt(u * u + v * v));
         const bool finite = isfinite(w.H) && isfinite((double)w.p) && isfinite((double)w.mx) &&
-                            isfinite((double)w.my) && isfinite((double)w.C);
+                            isfinite((double)w.my) && isfinite(w.C);
         acc[5] += finite ? 0.0 : 1.0;
         if (i == ic) acc[6] += Fs;
     }
