@@ -205,6 +205,53 @@ int eulbfs_destroy(eulbfs_t h);
  * failure of a create or host-only call on this thread). */
 const char* eulbfs_last_error(eulbfs_t h);
 
+/* ---------------------------------------------------------------------------
+ * Batched solves (many independent grids of uneven size advanced by one
+ * persistent launch per RK stage).  A batch owns one device arena; requests
+ * are admitted into slots while their footprint fits the HBM budget.
+ * ------------------------------------------------------------------------- */
+typedef struct eulbfs_batch* eulbfs_batch_t;
+
+/* Create a batch with an arena of hbm_budget bytes (allocated by the library
+ * when d_ws is NULL, else carved from d_ws of ws_bytes >= hbm_budget, 256-byte
+ * aligned) and at most max_slots resident requests, all of one precision
+ * (EULBFS_FP64 or EULBFS_FP32).  Work is enqueued on hip_stream. */
+int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision, void* d_ws,
+                        size_t ws_bytes, void* hip_stream, eulbfs_batch_t* out);
+
+/* Footprint in the arena of one request with these parameters. */
+size_t eulbfs_batch_request_bytes(const eulbfs_params* prm);
+
+/* Admit a request that will run nsteps steps: copies its initial state into
+ * the arena (synchronises the stream).  EULBFS_EBUSY when no slot or not
+ * enough contiguous arena is free; EULBFS_EINVAL for bad parameters or a
+ * precision that differs from the batch's.  *slot receives the slot index.
+ * The request steps with the batched kernel (tile 32 x 8) whatever its
+ * kernel and tile fields say. */
+int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_init* init,
+                       int64_t nsteps, int32_t* slot);
+
+/* Advance every resident unfinished request by the same number of steps:
+ * min(steps, the smallest number of steps any of them still has to run),
+ * with one persistent launch per RK stage (per h/g lattice present) over the
+ * tiles of all of them.  Asynchronous: enqueues and returns. */
+int eulbfs_batch_tick(eulbfs_batch_t b, int32_t steps);
+
+/* Slots whose requests have finished on the device (up to cap), in slot
+ * order.  Does not block. */
+int eulbfs_batch_poll(eulbfs_batch_t b, int32_t* done, int32_t cap, int32_t* n);
+
+/* eulbfs_query on the request in a slot (synchronises). */
+int eulbfs_batch_query(eulbfs_batch_t b, int32_t slot, int32_t what, void* out, size_t bytes,
+                       int32_t out_on_device);
+
+/* Free a slot and its arena range (synchronises). */
+int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot);
+
+int eulbfs_batch_destroy(eulbfs_batch_t b);
+
+const char* eulbfs_batch_last_error(eulbfs_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -248,6 +248,9 @@ hipError_t to_double(const R* src, size_t spitch, int w, int h, double* dst, hip
 
 }  // namespace
 
+// Steps per captured graph of a single solver.
+constexpr int GRAPH_STEPS = 8;
+
 struct eulbfs_solver {
     eulbfs_params prm;
     DevParams dp;
@@ -259,12 +262,16 @@ struct eulbfs_solver {
     int64_t steps = 0;
     bool poisoned = false;
     std::string err;
+    // GRAPH_STEPS steps captured once and replayed (kernel nodes only)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_failed = false;
 };
 
 namespace {
 
 template <typename R>
-int enqueue_steps(eulbfs_solver* h, int64_t n)
+int enqueue_raw(eulbfs_solver* h, int64_t n)
 {
     std::string* err = &h->err;
     const DevParams& P = h->dp;
@@ -284,6 +291,47 @@ int enqueue_steps(eulbfs_solver* h, int64_t n)
             HIP_TRY(launch_stage_fused<R>(P, h->tile, K3, WB, W0, W0, fsdot, h->stream));
         }
     }
+    return EULBFS_OK;
+}
+
+// Capture GRAPH_STEPS steps into a graph (once per solver).  Capture needs a
+// created stream; on the legacy default stream, or if capture fails, the
+// solver keeps launching eagerly.
+template <typename R>
+bool ensure_graph(eulbfs_solver* h)
+{
+    if (h->graph_exec) return true;
+    if (h->graph_failed || h->stream == nullptr) return false;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        h->graph_failed = true;
+        (void)hipGetLastError();
+        return false;
+    }
+    const int rc = enqueue_raw<R>(h, GRAPH_STEPS);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != EULBFS_OK || e != hipSuccess || !g ||
+        hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        h->graph_exec = nullptr;
+        h->graph_failed = true;
+        (void)hipGetLastError();
+        return false;
+    }
+    h->graph = g;
+    return true;
+}
+
+template <typename R>
+int enqueue_steps(eulbfs_solver* h, int64_t n)
+{
+    std::string* err = &h->err;
+    int64_t left = n;
+    if (n >= 2 * GRAPH_STEPS && ensure_graph<R>(h)) {
+        for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS) HIP_TRY(hipGraphLaunch(h->graph_exec, h->stream));
+    }
+    const int rc = enqueue_raw<R>(h, left);
+    if (rc != EULBFS_OK) return rc;
     h->steps += n;
     return EULBFS_OK;
 }
@@ -562,6 +610,8 @@ int eulbfs_destroy(eulbfs_t h)
 {
     if (!h) return EULBFS_OK;
     if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     delete h;
     return EULBFS_OK;
@@ -571,6 +621,383 @@ const char* eulbfs_last_error(eulbfs_t h)
 {
     if (!h) return g_thread_err.c_str();
     return h->err.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched solves
+//
+// A batch owns one arena of device memory.  Each admitted request becomes a
+// solver whose workspace is a range of the arena, so initialisation, queries
+// and checkpoints are the single-solver code.  A tick advances every resident
+// unfinished request by the same number of steps with one persistent launch
+// per RK stage over the concatenated tile lists of all of them.
+// ===========================================================================
+namespace {
+
+struct Slot {
+    eulbfs_solver* s = nullptr;
+    size_t off = 0, bytes = 0;
+    int64_t nsteps = 0, done = 0;
+    int64_t finish_tick = -1;  // tick whose launches complete the request
+};
+
+struct TickEvent {
+    hipEvent_t ev = nullptr;
+    int64_t tick = -1;
+};
+
+}  // namespace
+
+struct eulbfs_batch {
+    size_t budget = 0;
+    int max_slots = 0;
+    int precision = EULBFS_FP64;
+    char* base = nullptr;  // whole allocation: tables, then the arena
+    bool own = false;
+    hipStream_t stream = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<Slot> slots;
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, bytes), sorted by offset
+    // device tables (two sets, alternating between ticks)
+    char* d_desc[2] = {nullptr, nullptr};
+    int* d_tiles[2] = {nullptr, nullptr};
+    size_t desc_bytes = 0;
+    int tile_cap = 0;
+    // pinned host copies of the tables
+    char* h_desc[2] = {nullptr, nullptr};
+    int* h_tiles[2] = {nullptr, nullptr};
+    hipEvent_t upload_done[2] = {nullptr, nullptr};
+    int parity = 0;
+    int grid_blocks = 0;
+    int64_t tick = 0;
+    std::vector<TickEvent> events;  // recent ticks
+    int64_t completed_tick = 0;     // every tick < completed_tick has completed
+    std::string err;
+};
+
+namespace {
+
+size_t arena_alloc(eulbfs_batch* b, size_t bytes)
+{
+    for (size_t k = 0; k < b->free_list.size(); ++k) {
+        auto& f = b->free_list[k];
+        if (f.second >= bytes) {
+            const size_t off = f.first;
+            f.first += bytes;
+            f.second -= bytes;
+            if (f.second == 0) b->free_list.erase(b->free_list.begin() + k);
+            return off;
+        }
+    }
+    return SIZE_MAX;
+}
+
+void arena_free(eulbfs_batch* b, size_t off, size_t bytes)
+{
+    auto& fl = b->free_list;
+    auto it = std::lower_bound(fl.begin(), fl.end(), std::make_pair(off, (size_t)0));
+    it = fl.insert(it, {off, bytes});
+    // merge with the next and the previous ranges
+    if (it + 1 != fl.end() && it->first + it->second == (it + 1)->first) {
+        it->second += (it + 1)->second;
+        fl.erase(it + 1);
+    }
+    if (it != fl.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+        (it - 1)->second += it->second;
+        fl.erase(it);
+    }
+}
+
+eulbfs_params batch_view(const eulbfs_params* prm)
+{
+    eulbfs_params p = *prm;
+    p.kernel = EULBFS_KERNEL_FUSED;  // batches step with the batched fused kernel
+    p.tile_x = 0;
+    p.tile_y = 0;
+    return p;
+}
+
+size_t desc_size(int precision)
+{
+    return precision == EULBFS_FP32 ? sizeof(BatchDesc<float>) : sizeof(BatchDesc<double>);
+}
+
+// Mark ticks whose event has completed (non-blocking unless wait).
+void batch_progress(eulbfs_batch* b, bool wait)
+{
+    while (!b->events.empty()) {
+        TickEvent& te = b->events.front();
+        const hipError_t e = wait ? hipEventSynchronize(te.ev) : hipEventQuery(te.ev);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        b->completed_tick = te.tick + 1;
+        (void)hipEventDestroy(te.ev);
+        b->events.erase(b->events.begin());
+    }
+}
+
+template <typename R>
+int batch_tick(eulbfs_batch* b, int32_t steps)
+{
+    std::string* err = &b->err;
+    // active requests and the common step count of this tick
+    std::vector<int> act;
+    int64_t s_eff = steps;
+    for (int k = 0; k < b->max_slots; ++k) {
+        const Slot& sl = b->slots[k];
+        if (sl.s && sl.done < sl.nsteps) {
+            act.push_back(k);
+            s_eff = std::min<int64_t>(s_eff, sl.nsteps - sl.done);
+        }
+    }
+    if (act.empty() || s_eff <= 0) return EULBFS_OK;
+    const int par = b->parity;
+    b->parity ^= 1;
+    if (b->upload_done[par]) HIP_TRY(hipEventSynchronize(b->upload_done[par]));
+    BatchDesc<R>* hd = reinterpret_cast<BatchDesc<R>*>(b->h_desc[par]);
+    int* ht = b->h_tiles[par];
+    // tiles ordered by lattice (one launch per lattice present)
+    int ntiles[2] = {0, 0}, nd = 0;
+    std::vector<int> order;
+    for (int lat = 0; lat < 2; ++lat)
+        for (int k : act)
+            if ((b->slots[k].s->prm.lattice_hg == 5) == (lat == 1)) order.push_back(k);
+    // each lattice group is launched on its own sub-list of tiles, so a
+    // request's first tile is counted from the start of its group
+    int tile_total = 0;
+    for (int k : order) {
+        eulbfs_solver* h = b->slots[k].s;
+        const int tx = (h->prm.nx + BATCH_TX - 1) / BATCH_TX, ty = (h->prm.ny + BATCH_TY - 1) / BATCH_TY;
+        if (tile_total + tx * ty > b->tile_cap) return set_err(err, EULBFS_ENOMEM, "batch tile table full");
+        const int group = h->prm.lattice_hg == 5 ? 1 : 0;
+        BatchDesc<R>& D = hd[nd];
+        D.P = h->dp;
+        D.W[0] = state_at<R>(h->ws, h->L.W0, h->L);
+        D.W[1] = state_at<R>(h->ws, h->L.WA, h->L);
+        D.W[2] = state_at<R>(h->ws, h->L.WB, h->L);
+        D.fsdot = (R*)(h->ws + h->L.fsdot);
+        D.tiles_x = tx;
+        D.tile0 = ntiles[group];
+        for (int t = 0; t < tx * ty; ++t) ht[tile_total + t] = nd;
+        tile_total += tx * ty;
+        ntiles[group] += tx * ty;
+        ++nd;
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_desc[par], hd, (size_t)nd * sizeof(BatchDesc<R>), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_tiles[par], ht, (size_t)tile_total * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipEventRecord(b->upload_done[par], b->stream));
+    const BatchDesc<R>* dd = reinterpret_cast<const BatchDesc<R>*>(b->d_desc[par]);
+    const StageCoef K[3] = {{0.0, 1.0, 1.0, 0}, {0.75, 0.25, 0.25, 0}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 1}};
+    for (int64_t st = 0; st < s_eff; ++st)
+        for (int stage = 0; stage < 3; ++stage) {
+            if (ntiles[0])
+                HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par], ntiles[0], 9, K[stage], stage, b->grid_blocks,
+                                                b->stream));
+            if (ntiles[1])
+                HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + ntiles[0], ntiles[1], 5, K[stage], stage,
+                                                b->grid_blocks, b->stream));
+        }
+    TickEvent te;
+    HIP_TRY(hipEventCreateWithFlags(&te.ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(te.ev, b->stream));
+    te.tick = b->tick;
+    b->events.push_back(te);
+    for (int k : act) {
+        Slot& sl = b->slots[k];
+        sl.done += s_eff;
+        sl.s->steps += s_eff;
+        if (sl.done >= sl.nsteps) sl.finish_tick = b->tick;
+    }
+    ++b->tick;
+    return EULBFS_OK;
+}
+
+Slot* batch_slot(eulbfs_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].s) return nullptr;
+    return &b->slots[slot];
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t eulbfs_batch_request_bytes(const eulbfs_params* prm)
+{
+    if (!check(prm).empty()) return 0;
+    const eulbfs_params p = batch_view(prm);
+    return align_up(make_layout(&p).total);
+}
+
+int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision, void* d_ws, size_t ws_bytes,
+                        void* hip_stream, eulbfs_batch_t* out)
+{
+    std::string* err = nullptr;
+    if (!out) return set_err(err, EULBFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots <= 0 || max_slots > 65536) return set_err(err, EULBFS_EINVAL, "max_slots must be in 1..65536");
+    if (precision != EULBFS_FP64 && precision != EULBFS_FP32) return set_err(err, EULBFS_EINVAL, "unknown precision");
+    if (hbm_budget < ((size_t)1 << 20)) return set_err(err, EULBFS_EINVAL, "hbm_budget below 1 MiB");
+    eulbfs_batch* b = new eulbfs_batch();
+    b->budget = hbm_budget;
+    b->max_slots = max_slots;
+    b->precision = precision;
+    b->stream = (hipStream_t)hip_stream;
+    b->slots.resize(max_slots);
+    b->desc_bytes = align_up((size_t)max_slots * desc_size(precision));
+    // a tile holds BATCH_TX * BATCH_TY cells of at least 88 bytes (three FP32-mode copies of W + dF_s/dt)
+    b->tile_cap = max_slots + (int)std::min<size_t>(hbm_budget / ((size_t)BATCH_TX * BATCH_TY * 88), 1 << 26);
+    const size_t tiles_bytes = align_up((size_t)b->tile_cap * sizeof(int));
+    const size_t tables = 2 * (b->desc_bytes + tiles_bytes);
+    if (hbm_budget <= tables) {
+        delete b;
+        return set_err(err, EULBFS_EINVAL, "hbm_budget too small for the batch tables");
+    }
+    if (d_ws) {
+        if (ws_bytes < hbm_budget || ((uintptr_t)d_ws % ALIGN) != 0) {
+            delete b;
+            return set_err(err, EULBFS_EINVAL, "workspace must be >= hbm_budget bytes and 256-byte aligned");
+        }
+        b->base = (char*)d_ws;
+    } else {
+        const hipError_t e = hipMalloc(&b->base, hbm_budget);
+        if (e != hipSuccess) {
+            delete b;
+            return set_err(err, EULBFS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        b->own = true;
+    }
+    char* p = b->base;
+    for (int k = 0; k < 2; ++k) {
+        b->d_desc[k] = p;
+        p += b->desc_bytes;
+        b->d_tiles[k] = (int*)p;
+        p += tiles_bytes;
+    }
+    b->arena = p;
+    b->arena_bytes = hbm_budget - tables;
+    b->free_list.push_back({0, b->arena_bytes});
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k) {
+        ok &= hipHostMalloc((void**)&b->h_desc[k], b->desc_bytes, hipHostMallocDefault) == hipSuccess;
+        ok &= hipHostMalloc((void**)&b->h_tiles[k], tiles_bytes, hipHostMallocDefault) == hipSuccess;
+        ok &= hipEventCreateWithFlags(&b->upload_done[k], hipEventDisableTiming) == hipSuccess;
+    }
+    int dev = 0, cus = 0;
+    ok &= hipGetDevice(&dev) == hipSuccess;
+    ok &= hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
+    if (!ok) {
+        eulbfs_batch_destroy(b);
+        return set_err(err, EULBFS_EDEVICE, "batch set-up failed (pinned tables, events or device query)");
+    }
+    b->grid_blocks = cus * (precision == EULBFS_FP32 ? 4 : 3);  // resident workgroups of the batched kernel
+    *out = b;
+    return EULBFS_OK;
+}
+
+int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_init* init, int64_t nsteps,
+                       int32_t* slot)
+{
+    if (!b) return set_err(nullptr, EULBFS_EINVAL, "batch is NULL");
+    std::string* err = &b->err;
+    if (!slot) return set_err(err, EULBFS_EINVAL, "slot is NULL");
+    *slot = -1;
+    const std::string e = check(prm);
+    if (!e.empty()) return set_err(err, EULBFS_EINVAL, e);
+    if (prm->precision != b->precision) return set_err(err, EULBFS_EINVAL, "request precision differs from the batch");
+    if (nsteps <= 0) return set_err(err, EULBFS_EINVAL, "nsteps must be > 0");
+    int k = 0;
+    while (k < b->max_slots && b->slots[k].s) ++k;
+    if (k == b->max_slots) return set_err(err, EULBFS_EBUSY, "no free slot");
+    const eulbfs_params p = batch_view(prm);
+    const size_t bytes = align_up(make_layout(&p).total);
+    const size_t off = arena_alloc(b, bytes);
+    if (off == SIZE_MAX) return set_err(err, EULBFS_EBUSY, "not enough free arena for this request");
+    eulbfs_solver* h = nullptr;
+    const int rc = eulbfs_create(&p, init, b->arena + off, bytes, b->stream, &h);
+    if (rc != EULBFS_OK) {
+        arena_free(b, off, bytes);
+        return set_err(err, rc, g_thread_err);
+    }
+    Slot& sl = b->slots[k];
+    sl.s = h;
+    sl.off = off;
+    sl.bytes = bytes;
+    sl.nsteps = nsteps;
+    sl.done = 0;
+    sl.finish_tick = -1;
+    *slot = k;
+    return EULBFS_OK;
+}
+
+int eulbfs_batch_tick(eulbfs_batch_t b, int32_t steps)
+{
+    if (!b) return set_err(nullptr, EULBFS_EINVAL, "batch is NULL");
+    if (steps <= 0) return set_err(&b->err, EULBFS_EINVAL, "steps must be > 0");
+    return b->precision == EULBFS_FP32 ? batch_tick<float>(b, steps) : batch_tick<double>(b, steps);
+}
+
+int eulbfs_batch_poll(eulbfs_batch_t b, int32_t* done, int32_t cap, int32_t* n)
+{
+    if (!b) return set_err(nullptr, EULBFS_EINVAL, "batch is NULL");
+    if (!n || (cap > 0 && !done)) return set_err(&b->err, EULBFS_EINVAL, "bad output arguments");
+    batch_progress(b, false);
+    int cnt = 0;
+    for (int k = 0; k < b->max_slots && cnt < cap; ++k) {
+        const Slot& sl = b->slots[k];
+        if (sl.s && sl.done >= sl.nsteps && sl.finish_tick >= 0 && sl.finish_tick < b->completed_tick)
+            done[cnt++] = k;
+    }
+    *n = cnt;
+    return EULBFS_OK;
+}
+
+int eulbfs_batch_query(eulbfs_batch_t b, int32_t slot, int32_t what, void* out, size_t bytes, int32_t out_on_device)
+{
+    Slot* sl = batch_slot(b, slot);
+    if (!sl) return set_err(b ? &b->err : nullptr, EULBFS_EINVAL, "no request in this slot");
+    const int rc = eulbfs_query(sl->s, what, out, bytes, out_on_device);
+    if (rc != EULBFS_OK) b->err = sl->s->err;
+    return rc;
+}
+
+int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot)
+{
+    Slot* sl = batch_slot(b, slot);
+    if (!sl) return set_err(b ? &b->err : nullptr, EULBFS_EINVAL, "no request in this slot");
+    (void)hipStreamSynchronize(b->stream);  // its planes may still be in use by enqueued launches
+    eulbfs_destroy(sl->s);
+    arena_free(b, sl->off, sl->bytes);
+    *sl = Slot();
+    return EULBFS_OK;
+}
+
+int eulbfs_batch_destroy(eulbfs_batch_t b)
+{
+    if (!b) return EULBFS_OK;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& sl : b->slots)
+        if (sl.s) eulbfs_destroy(sl.s);
+    for (auto& te : b->events) (void)hipEventDestroy(te.ev);
+    for (int k = 0; k < 2; ++k) {
+        if (b->h_desc[k]) (void)hipHostFree(b->h_desc[k]);
+        if (b->h_tiles[k]) (void)hipHostFree(b->h_tiles[k]);
+        if (b->upload_done[k]) (void)hipEventDestroy(b->upload_done[k]);
+    }
+    if (b->own && b->base) (void)hipFree(b->base);
+    delete b;
+    return EULBFS_OK;
+}
+
+const char* eulbfs_batch_last_error(eulbfs_batch_t b)
+{
+    if (!b) return g_thread_err.c_str();
+    return b->err.c_str();
 }
 
 }  // extern "C"

@@ -28,6 +28,20 @@ struct SplitScratch {
 
 enum { TILE_32x8 = 0, TILE_64x4 = 1, TILE_16x16 = 2, TILE_64x8 = 3, NTILES = 4 };
 
+constexpr int NXCD = 8;  // accelerator complex dies of an MI355X, each with its own L2
+
+// One request of a batch: its constants, its three copies of W (W^n, W1, W2)
+// and its dF_s/dt plane, and where its tiles start in the batch's tile list.
+constexpr int BATCH_TX = 32, BATCH_TY = 8;
+template <typename R>
+struct BatchDesc {
+    DevParams P;
+    State<R> W[3];
+    R* fsdot;
+    int tiles_x;
+    int tile0;
+};
+
 constexpr int NRED = 7;  // sum rho, sum C, sum H, sum F_s, max |u|, non-finite, tip column
 
 template <typename R>
@@ -45,6 +59,9 @@ hipError_t launch_set_conserved(const DevParams& P, const double* w6, const Stat
 template <typename R>
 hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, int what, double* dst,
                          hipStream_t st);
+template <typename R>
+hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice,
+                                const StageCoef& K, int stage, int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,
                          hipStream_t st);

@@ -14,6 +14,8 @@
 //   k_init          primitive initial fields -> conserved vector.
 //   k_export        conserved or derived field -> dense double plane.
 //   k_reduce_*      FP64 integrals, deterministic two-pass wave reduction.
+#include <algorithm>
+
 #include "eulbfs_device.h"
 #include "eulbfs_internal.h"
 
@@ -83,9 +85,11 @@ struct FusedLds {
     static constexpr size_t BYTES_U = BYTES_W > BYTES_F ? BYTES_W : BYTES_F;
 };
 
+// One tile of one stage: cells [i0, i0+TX) x [j0, j0+TY) of the grid described
+// by P.  Every thread of the workgroup must call it (it synchronises).
 template <typename R, int LAT, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
-    k_stage_fused(DevParams P, StageCoef K, State<R> in, State<R> Wn, State<R> out, R* fsdot)
+__device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& K, const State<R>& in,
+                                           const State<R>& Wn, const State<R>& out, R* fsdot, int i0, int j0)
 {
     using L = FusedLds<R, TX, TY>;
     constexpr int NT = TX * TY;
@@ -98,7 +102,7 @@ __global__ void __launch_bounds__(TX* TY)
     R* sF = reinterpret_cast<R*>(sU);                                          // 5 planes of NFX+NFY
 
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    __syncthreads();  // the LDS of a previous tile of this workgroup is free
 
     // 1. stage W of the tile and three halo layers
     for (int q = tid; q < W3 * H3; q += NT) {
@@ -178,7 +182,7 @@ __global__ void __launch_bounds__(TX* TY)
     // 4. cell update
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
-    if (i >= P.nx || j >= P.ny) return;
+    if (i < 0 || j < 0 || i >= P.nx || j >= P.ny) return;  // no barrier follows in this tile
     const int fl = ty * (TX + 1) + tx;
     const int fb = NFX + ty * TX + tx;
     const R idx = R(1.0 / P.dx);
@@ -199,6 +203,38 @@ __global__ void __launch_bounds__(TX* TY)
     const size_t q = (size_t)j * P.pitch + i;
     const Cons<R> wk = read_cell(in, P.pitch, i, j);
     cell_update(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, (R*)nullptr, 0, q);
+}
+
+// One stage of one grid.  Workgroups are dispatched round-robin over the
+// eight XCDs of the chip, each with its own L2; giving every XCD a
+// contiguous run of tiles keeps the halo rows a tile shares with its
+// neighbours in the same L2.
+template <typename R, int LAT, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    k_stage_fused(DevParams P, StageCoef K, State<R> in, State<R> Wn, State<R> out, R* fsdot, int tiles_x,
+                  int ntiles, int per_xcd)
+{
+    const int b = blockIdx.x;
+    const int t = (b % NXCD) * per_xcd + b / NXCD;
+    if (t >= ntiles) return;
+    stage_tile<R, LAT, TX, TY>(P, K, in, Wn, out, fsdot, (t % tiles_x) * TX, (t / tiles_x) * TY);
+}
+
+// One stage of every grid of a batch.  tile_req maps a tile of the
+// concatenated tile list to its request; workgroups loop over the tiles
+// (persistent grid), so one launch covers grids of any size mix.
+template <typename R, int LAT, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    k_stage_batched(const BatchDesc<R>* __restrict__ descs, const int* __restrict__ tile_req, int ntiles,
+                    StageCoef K, int stage)
+{
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchDesc<R>& D = descs[tile_req[t]];
+        const int lt = t - D.tile0;  // tile index within its request, 0 <= lt < tiles of the request
+        const State<R>& in = D.W[stage];
+        const State<R>& out = D.W[stage == 2 ? 0 : stage + 1];
+        stage_tile<R, LAT, TX, TY>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX, (lt / D.tiles_x) * TY);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,8 +553,26 @@ template <typename R, int LAT, int TX, int TY>
 static hipError_t launch_fused_t(const DevParams& P, const StageCoef& K, const State<R>& in, const State<R>& Wn,
                                  const State<R>& out, R* fsdot, hipStream_t st)
 {
-    dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k_stage_fused<R, LAT, TX, TY>), grid, dim3(TX * TY), 0, st, P, K, in, Wn, out, fsdot);
+    const int tiles_x = (P.nx + TX - 1) / TX, tiles_y = (P.ny + TY - 1) / TY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + NXCD - 1) / NXCD;
+    hipLaunchKernelGGL((k_stage_fused<R, LAT, TX, TY>), dim3(per_xcd * NXCD), dim3(TX * TY), 0, st, P, K, in, Wn,
+                       out, fsdot, tiles_x, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice,
+                                const StageCoef& K, int stage, int grid, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int g = std::min(grid, ntiles);
+    if (lattice == 5)
+        hipLaunchKernelGGL((k_stage_batched<R, 5, BATCH_TX, BATCH_TY>), dim3(g), dim3(BATCH_TX * BATCH_TY), 0, st,
+                           descs, tile_req, ntiles, K, stage);
+    else
+        hipLaunchKernelGGL((k_stage_batched<R, 9, BATCH_TX, BATCH_TY>), dim3(g), dim3(BATCH_TX * BATCH_TY), 0, st,
+                           descs, tile_req, ntiles, K, stage);
     return hipGetLastError();
 }
 
@@ -613,7 +667,9 @@ hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial,
     template hipError_t launch_set_conserved<R>(const DevParams&, const double*, const State<R>&, R*, int,         \
                                                 hipStream_t);                                                      \
     template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
-    template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);
+    template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);   \
+    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, const StageCoef&, int,  \
+                                                int, hipStream_t);
 
 EULBFS_INSTANTIATE(double)
 EULBFS_INSTANTIATE(float)

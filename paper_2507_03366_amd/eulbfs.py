@@ -272,3 +272,151 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Batch API
+# ---------------------------------------------------------------------------
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        vp, sz = ct.c_void_p, ct.c_size_t
+        pp = ct.POINTER(eulbfs_params)
+        L.eulbfs_batch_create.argtypes = [sz, ct.c_int32, ct.c_int32, vp, sz, vp, ct.POINTER(vp)]
+        L.eulbfs_batch_request_bytes.argtypes = [pp]
+        L.eulbfs_batch_request_bytes.restype = sz
+        L.eulbfs_batch_admit.argtypes = [vp, pp, ct.POINTER(eulbfs_init), ct.c_int64, ct.POINTER(ct.c_int32)]
+        L.eulbfs_batch_tick.argtypes = [vp, ct.c_int32]
+        L.eulbfs_batch_poll.argtypes = [vp, ct.POINTER(ct.c_int32), ct.c_int32, ct.POINTER(ct.c_int32)]
+        L.eulbfs_batch_query.argtypes = [vp, ct.c_int32, ct.c_int32, vp, sz, ct.c_int32]
+        L.eulbfs_batch_release.argtypes = [vp, ct.c_int32]
+        L.eulbfs_batch_destroy.argtypes = [vp]
+        L.eulbfs_batch_last_error.argtypes = [vp]
+        L.eulbfs_batch_last_error.restype = ct.c_char_p
+        for f in ("eulbfs_batch_create", "eulbfs_batch_admit", "eulbfs_batch_tick", "eulbfs_batch_poll",
+                  "eulbfs_batch_query", "eulbfs_batch_release", "eulbfs_batch_destroy"):
+            getattr(L, f).restype = ct.c_int
+        L._batch_ready = True
+    return L
+
+
+def _braise(rc, b=None):
+    if rc != OK:
+        msg = _batch_lib().eulbfs_batch_last_error(b)
+        raise EulbfsError(rc, msg.decode() if msg else "")
+
+
+def eulbfs_batch_request_bytes(P: eulbfs_params) -> int:
+    return int(_batch_lib().eulbfs_batch_request_bytes(ct.byref(P)))
+
+
+def eulbfs_batch_create(hbm_budget: int, max_slots: int, precision: int, workspace=None, stream=None):
+    ws = ct.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = ct.c_void_p(stream.cuda_stream) if stream is not None else None
+    b = ct.c_void_p()
+    _braise(_batch_lib().eulbfs_batch_create(int(hbm_budget), int(max_slots), int(precision), ws, ws_bytes, st,
+                                             ct.byref(b)))
+    return b
+
+
+def eulbfs_batch_admit(b, P: eulbfs_params, init_planes: np.ndarray, nsteps: int, kind: int = INIT_PRIMITIVE):
+    """Returns the slot index, or None when the batch is full (EBUSY)."""
+    arr = np.ascontiguousarray(init_planes, dtype=np.float64)
+    init = eulbfs_init()
+    init.kind, init.on_device = kind, 0
+    init.planes = arr.ctypes.data_as(ct.POINTER(ct.c_double))
+    slot = ct.c_int32(-1)
+    rc = _batch_lib().eulbfs_batch_admit(b, ct.byref(P), ct.byref(init), int(nsteps), ct.byref(slot))
+    if rc == EBUSY:
+        return None
+    _braise(rc, b)
+    return slot.value
+
+
+def eulbfs_batch_tick(b, steps: int) -> None:
+    _braise(_batch_lib().eulbfs_batch_tick(b, int(steps)), b)
+
+
+def eulbfs_batch_poll(b, cap: int = 4096):
+    out = (ct.c_int32 * cap)()
+    n = ct.c_int32(0)
+    _braise(_batch_lib().eulbfs_batch_poll(b, out, cap, ct.byref(n)), b)
+    return [out[k] for k in range(n.value)]
+
+
+def eulbfs_batch_query(b, slot: int, what: int, nx: int, ny: int) -> np.ndarray:
+    if what == SCALAR_DIAG:
+        out = np.zeros(NDIAG)
+    elif what == FIELD["W_ALL"]:
+        out = np.zeros((6, ny, nx))
+    else:
+        out = np.zeros((ny, nx))
+    _braise(_batch_lib().eulbfs_batch_query(b, slot, what, out.ctypes.data_as(ct.c_void_p), out.nbytes, 0), b)
+    return out
+
+
+def eulbfs_batch_release(b, slot: int) -> None:
+    _braise(_batch_lib().eulbfs_batch_release(b, slot), b)
+
+
+def eulbfs_batch_destroy(b) -> None:
+    _batch_lib().eulbfs_batch_destroy(b)
+
+
+def eulbfs_batch_last_error(b=None) -> str:
+    m = _batch_lib().eulbfs_batch_last_error(b)
+    return m.decode() if m else ""
+
+
+class Batch:
+    """Many grids resident in one device arena, advanced together."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, precision: int = FP32, device="cuda:0", stream=None):
+        import torch
+
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(hbm_budget) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.precision = precision
+        self.stream = stream
+        self.b = eulbfs_batch_create(hbm_budget, max_slots, precision, self.workspace[off:off + int(hbm_budget)],
+                                     stream)
+        self.shapes = {}
+
+    def admit(self, pr, state, nsteps: int):
+        P = params_from_problem(pr, precision=self.precision)
+        planes = np.concatenate([a.ravel() for a in state.planes()])
+        slot = eulbfs_batch_admit(self.b, P, planes, nsteps)
+        if slot is not None:
+            self.shapes[slot] = (pr.nx, pr.ny)
+        return slot
+
+    def tick(self, steps: int):
+        eulbfs_batch_tick(self.b, steps)
+
+    def poll(self):
+        return eulbfs_batch_poll(self.b)
+
+    def conserved(self, slot: int) -> np.ndarray:
+        nx, ny = self.shapes[slot]
+        return eulbfs_batch_query(self.b, slot, FIELD["W_ALL"], nx, ny)
+
+    def diagnostics(self, slot: int) -> dict:
+        nx, ny = self.shapes[slot]
+        return dict(zip(DIAG_NAMES, eulbfs_batch_query(self.b, slot, SCALAR_DIAG, nx, ny)))
+
+    def release(self, slot: int):
+        eulbfs_batch_release(self.b, slot)
+        self.shapes.pop(slot, None)
+
+    def close(self):
+        if self.b is not None:
+            eulbfs_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,144 @@
+"""Batched solves through the C ABI: many uneven grids advanced by one
+persistent launch per RK stage.  Each request must match the FP64 oracle,
+and must be bitwise the same alone in a batch and in a mix (the per-cell
+arithmetic does not depend on the other requests)."""
+import numpy as np
+import pytest
+
+from paper_2507_03366_amd import eulbfs as E
+from paper_2507_03366_amd import problems as PB
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = (("H", [0]), ("p", [1]), ("M", [2, 3]), ("C", [4]))
+
+
+def rel_l2(a, b):
+    den = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / den) if den > 0 else float(np.linalg.norm(a.ravel()))
+
+
+def errors(w, ref):
+    return {k: rel_l2(w[ks], ref[ks]) for k, ks in GROUPS}
+
+
+def _requests():
+    reqs = []
+    pr, st = PB.static_droplet(n=64, R=16)
+    reqs.append((pr.replace(sigma=0.015625), st))
+    pr, st = PB.static_droplet(n=64, R=16, lattice_hg=5)
+    pr = pr.replace(nx=90, ny=70, sigma=0.015625)
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr)
+    st.C = PB.droplet_profile(X, Y, 45.0, 0.0, 18.0, 4.0)
+    reqs.append((pr, st))
+    reqs.append(PB.three_phase_stefan())
+    reqs.append(PB.conductive_freezing())
+    reqs.append(PB.impact_droplet(n=48, we=20.0, re=200.0))
+    return reqs
+
+
+def _run_batch(reqs, nsteps, precision=E.FP64, tick=10, budget=1 << 28):
+    import torch
+
+    b = E.Batch(budget, 16, precision=precision, stream=torch.cuda.Stream())
+    try:
+        slots = [b.admit(pr, st, n) for (pr, st), n in zip(reqs, nsteps)]
+        assert all(s is not None for s in slots)
+        while True:
+            pending = [s for s, n in zip(slots, nsteps) if b.diagnostics(s)["steps"] < n]
+            if not pending:
+                break
+            b.tick(tick)
+        torch.cuda.synchronize()
+        done = set(b.poll())
+        assert done == set(slots)
+        out = [b.conserved(s) for s in slots]
+        diags = [b.diagnostics(s) for s in slots]
+        for s in slots:
+            b.release(s)
+    finally:
+        b.close()
+    return out, diags
+
+
+def test_batch_matches_oracle_and_is_independent_of_the_mix(oracle):
+    reqs = _requests()
+    nsteps = [100, 80, 100, 60, 100]
+    mix, diags = _run_batch(reqs, nsteps)
+    oracle.set_threads(16)
+    for (pr, st), n, w, d in zip(reqs, nsteps, mix, diags):
+        assert d["steps"] == n
+        Wref, fsref = oracle.run(pr, st, n)
+        errs = errors(w[:5], Wref)
+        assert max(errs.values()) < 1e-11, (pr.nx, pr.ny, errs)
+    # each request alone in a batch: bitwise equal to its result in the mix
+    for k in (0, 1, 4):
+        alone, _ = _run_batch([reqs[k]], [nsteps[k]])
+        assert np.array_equal(alone[0], mix[k]), k
+
+
+def test_batch_agrees_with_single_solver():
+    pr, st = PB.static_droplet(n=64, R=16)
+    pr = pr.replace(sigma=0.015625)
+    w_b, _ = _run_batch([(pr, st)], [50])
+    s = E.Solver(pr, st, tile=(32, 8))
+    s.step(50)
+    w_s = s.conserved()
+    s.close()
+    assert max(errors(w_b[0][:5], w_s[:5]).values()) < 1e-13
+
+
+def test_batch_fp32_against_oracle(oracle):
+    reqs = _requests()[:3]
+    nsteps = [200, 200, 200]
+    out, _ = _run_batch(reqs, nsteps, precision=E.FP32)
+    oracle.set_threads(16)
+    for (pr, st), n, w in zip(reqs, nsteps, out):
+        Wref, _ = oracle.run(pr, st, n)
+        errs = errors(w[:5], Wref)
+        assert max(errs.values()) < 1e-4, errs
+
+
+def test_batch_admission_by_footprint():
+    import torch
+
+    pr, st = PB.static_droplet(n=256, R=64)
+    need = E.eulbfs_batch_request_bytes(E.params_from_problem(pr, precision=E.FP64))
+    b = E.Batch(int(need * 1.5) + (1 << 20), 8, precision=E.FP64, stream=torch.cuda.Stream())
+    try:
+        s0 = b.admit(pr, st, 10)
+        assert s0 is not None
+        assert b.admit(pr, st, 10) is None  # second copy does not fit
+        small, sst = PB.static_droplet(n=64, R=16)
+        s1 = b.admit(small, sst, 10)        # a small one still fits beside it
+        assert s1 is not None
+        b.release(s0)
+        s2 = b.admit(pr, st, 10)            # the freed range is reused
+        assert s2 is not None
+        # a request of another precision is refused
+        with pytest.raises(E.EulbfsError):
+            E.eulbfs_batch_admit(b.b, E.params_from_problem(small, precision=E.FP32),
+                                 np.concatenate([a.ravel() for a in sst.planes()]), 10)
+    finally:
+        b.close()
+
+
+def test_graph_replay_matches_eager_launches():
+    """Steps replayed from a captured graph (created stream) equal eager
+    launches on the default stream, across several calls with host work and
+    queries between the replays."""
+    import torch
+
+    pr, st = PB.film_freezing(n=64)
+    a = E.Solver(pr, st, stream=torch.cuda.Stream())
+    b = E.Solver(pr, st)  # legacy default stream: eager launches
+    try:
+        for n in (40, 16, 33, 64):
+            a.step(n)
+            b.step(n)
+            wa, wb = a.conserved(), b.conserved()
+            assert np.array_equal(wa, wb), n
+    finally:
+        a.close()
+        b.close()
