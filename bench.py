@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving", type=int, default=256, metavar="REQUESTS",
+                    help="requests of the continuous-batching serving mix (0: skip)")
+    ap.add_argument("--serving-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -173,6 +176,10 @@ def main():
                      "bytes_per_cell_step": bpcs},
         "diagnostics_after": {k: float(v) for k, v in diag.items()},
     }
+    if args.serving:
+        from paper_2507_03366_amd import serve as S
+
+        out["serving"] = S.run_mix(count=args.serving, nsteps=args.serving_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, st, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,210 @@
+"""Continuous-batching server for EULBFS solve requests.
+
+Requests arrive over time (Poisson arrivals), each a freezing droplet of its
+own grid size and parameters (Stefan number, supercooling, contact angle; half
+of them droplets impacting the cold wall at a drawn Weber and Reynolds
+number).  The server keeps every admitted request resident in one device
+arena (eulbfs_batch_*), admits waiting requests first-come first-served as
+slots and arena bytes free up, advances all resident requests together by
+one persistent launch per RK stage per tick, and retires each request as soon
+as its fixed step budget is done.  It reports solves per second and the
+p50/p99 time from arrival to result.
+
+The one-at-a-time baseline runs the same requests in FP64, each on its own
+solver (create, run, read the diagnostics, destroy), in arrival order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List
+
+import numpy as np
+
+from . import eulbfs as E
+from . import problems as PB
+
+SIZES = (64, 128, 256, 512)
+STATIC_SIGMA = PB.static_droplet()[0].sigma  # capillary number 0.01 of the 512 x 512 droplet
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str  # "static" or "impact"
+    n: int
+    nsteps: int
+    draws: dict
+    arrival: float = 0.0
+    problem: object = None
+    state: object = None
+
+
+def draw_requests(count: int, seed: int = 0, nsteps: int = 2000, sizes=SIZES) -> List[Request]:
+    """Seeded request mix: grid uniform over `sizes`, Ste ~ U[0.01, 1],
+    supercooling ~ U[0.1, 1], contact angle ~ U[60, 120] deg, impact with
+    probability 1/2 (We ~ U[5, 100], Re ~ U[100, 2000]); rho_s/rho_l = 0.917,
+    gas/liquid density ratio 1/1000."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.choice(sizes))
+        d = dict(ste=float(rng.uniform(0.01, 1.0)), supercool=float(rng.uniform(0.1, 1.0)),
+                 theta=float(rng.uniform(60.0, 120.0)))
+        impact = bool(rng.random() < 0.5)
+        if impact:
+            d.update(we=float(rng.uniform(5.0, 100.0)), re=float(rng.uniform(100.0, 2000.0)))
+        out.append(Request(rid=k, kind="impact" if impact else "static", n=n, nsteps=nsteps, draws=d))
+    return out
+
+
+def build(req: Request, precision: int):
+    d = req.draws
+    if req.kind == "impact":
+        pr, st = PB.impact_droplet(n=req.n, we=d["we"], re=d["re"], ste=d["ste"], supercool=d["supercool"],
+                                   theta_deg=d["theta"])
+    else:
+        pr, st = PB.static_droplet(n=req.n, R=req.n / 4, theta_deg=d["theta"], ste=d["ste"])
+        pr = pr.replace(sigma=STATIC_SIGMA)
+        st.T = np.where(st.C > 0.5, -d["supercool"], 0.0)
+    return pr.replace(precision=precision), st
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 1) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count)) if rate > 0 else np.zeros(count)
+
+
+def percentiles(lat):
+    a = np.asarray(lat)
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int = 2 << 30, max_slots: int = 64,
+          tick_steps: int = 100, stream=None) -> dict:
+    """Run the requests through one batch; arrival times are in seconds from
+    the start (requests[k].arrival).  Returns throughput and latency stats."""
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.Stream()
+    for r in requests:
+        if r.problem is None:
+            r.problem, r.state = build(r, precision)
+    batch = E.Batch(hbm_budget, max_slots, precision=precision, stream=stream)
+    waiting = sorted(requests, key=lambda r: r.arrival)
+    resident = {}  # slot -> request
+    finish = {}
+    admitted_at = {}
+    failed = []
+    t0 = time.perf_counter()
+    ticks = 0
+    enqueued = {}  # slot -> steps enqueued so far
+    try:
+        while waiting or resident:
+            now = time.perf_counter() - t0
+            # admit arrived requests, first come first served, while they fit
+            while waiting and waiting[0].arrival <= now:
+                r = waiting[0]
+                slot = batch.admit(r.problem, r.state, r.nsteps)
+                if slot is None:
+                    break
+                resident[slot] = r
+                enqueued[slot] = 0
+                admitted_at[r.rid] = time.perf_counter() - t0
+                waiting.pop(0)
+            if resident:
+                left = [r.nsteps - enqueued[sl] for sl, r in resident.items() if enqueued[sl] < r.nsteps]
+                if left:
+                    step = min(tick_steps, min(left))  # the tick's common step count
+                    batch.tick(tick_steps)
+                    ticks += 1
+                    for sl, r in resident.items():
+                        if enqueued[sl] < r.nsteps:
+                            enqueued[sl] += step
+                else:
+                    time.sleep(0.0005)  # everything resident is enqueued; wait for results
+                for slot in batch.poll():
+                    r = resident.pop(slot)
+                    d = batch.diagnostics(slot)
+                    finish[r.rid] = time.perf_counter() - t0
+                    if d["nonfinite"] != 0 or d["steps"] != r.nsteps:
+                        failed.append(r.rid)
+                    batch.release(slot)
+                    enqueued.pop(slot, None)
+            elif waiting:
+                time.sleep(max(0.0, min(waiting[0].arrival - now, 0.05)))
+    finally:
+        batch.close()
+    total = time.perf_counter() - t0
+    lat = [finish[r.rid] - r.arrival for r in requests]
+    p50, p99 = percentiles(lat)
+    cells = sum(r.problem.cells * r.nsteps for r in requests)
+    return {"solves": len(requests), "seconds": total, "solves_per_s": len(requests) / total,
+            "p50_s": p50, "p99_s": p99, "mean_s": float(np.mean(lat)), "ticks": ticks,
+            "cell_updates_per_s": cells / total, "failed": failed,
+            "precision": "fp32" if precision == E.FP32 else "fp64", "tick_steps": tick_steps,
+            "hbm_budget": hbm_budget, "max_slots": max_slots}
+
+
+def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None) -> dict:
+    """One request at a time on its own solver, in arrival order (arrivals are
+    honoured: a request cannot start before it arrives)."""
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    lat, failed = [], []
+    cells = 0
+    for r in sorted(requests, key=lambda q: q.arrival):
+        pr, st = build(r, precision)
+        now = time.perf_counter() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        s = E.Solver(pr, st, precision=precision, stream=stream)
+        try:
+            s.step(r.nsteps)
+            d = s.diagnostics()
+        finally:
+            s.close()
+        if d["nonfinite"] != 0:
+            failed.append(r.rid)
+        lat.append(time.perf_counter() - t0 - r.arrival)
+        cells += pr.cells * r.nsteps
+    total = time.perf_counter() - t0
+    p50, p99 = percentiles(lat)
+    return {"solves": len(requests), "seconds": total, "solves_per_s": len(requests) / total, "p50_s": p50,
+            "p99_s": p99, "mean_s": float(np.mean(lat)), "cell_updates_per_s": cells / total, "failed": failed,
+            "precision": "fp32" if precision == E.FP32 else "fp64"}
+
+
+def run_mix(count: int = 256, nsteps: int = 2000, seed: int = 0, load: float = 0.8, hbm_budget: int = 2 << 30,
+            max_slots: int = 64, tick_steps: int = 100, sizes=SIZES, with_sequential: bool = True) -> dict:
+    """The serving benchmark: (1) all requests at t = 0 through the batched
+    FP32 server (capacity), (2) Poisson arrivals at `load` times that capacity
+    (latency under load), (3) the sequential FP64 baseline on the burst."""
+    reqs = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
+    burst = serve(reqs, hbm_budget=hbm_budget, max_slots=max_slots, tick_steps=tick_steps)
+    rate = load * burst["solves_per_s"]
+    arr = poisson_arrivals(count, rate, seed=seed + 1)
+    reqs2 = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
+    for r, a in zip(reqs2, arr):
+        r.arrival = float(a)
+    loaded = serve(reqs2, hbm_budget=hbm_budget, max_slots=max_slots, tick_steps=tick_steps)
+    out = {"requests": count, "steps_per_request": nsteps, "seed": seed, "batched_fp32_burst": burst,
+           "batched_fp32_poisson": dict(loaded, arrival_rate_per_s=rate, load=load)}
+    if with_sequential:
+        reqs3 = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
+        out["sequential_fp64_burst"] = sequential(reqs3)
+        out["speedup_solves_per_s"] = burst["solves_per_s"] / out["sequential_fp64_burst"]["solves_per_s"]
+    return out
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+
+    n = int(sys.argv[1]) if len(sys.argv) > 1 else 256
+    print(json.dumps(run_mix(count=n)), flush=True)
