@@ -130,6 +130,9 @@ DevParams make_dev(const eulbfs_params* p)
     d.gx = p->gx;
     d.gy = p->gy;
     d.expansion = 1.0 - p->rho[0] / p->rho[1];
+    // fast paths give the same bits as the generic face arithmetic
+    d.fast = (0.5 * p->dx - p->delta_t == 0.0 ? FAST_HALF : 0) |
+             (p->cp[0] == p->cp[1] && p->cp[1] == p->cp[2] ? FAST_UCP : 0);
     return d;
 }
 
@@ -761,20 +764,25 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     if (b->upload_done[par]) HIP_TRY(hipEventSynchronize(b->upload_done[par]));
     BatchDesc<R>* hd = reinterpret_cast<BatchDesc<R>*>(b->h_desc[par]);
     int* ht = b->h_tiles[par];
-    // tiles ordered by lattice (one launch per lattice present)
-    int ntiles[2] = {0, 0}, nd = 0;
+    // tiles grouped by lattice and fast-path flags: one launch per group
+    // present, each on its own sub-list of tiles, so a request's first tile
+    // is counted from the start of its group
+    constexpr int NGROUP = 8;
+    auto group_of = [](const eulbfs_solver* h) {
+        return (h->prm.lattice_hg == 5 ? 4 : 0) + (h->dp.fast & (FAST_HALF | FAST_UCP));
+    };
+    int ntiles[NGROUP] = {}, first[NGROUP] = {}, nd = 0;
     std::vector<int> order;
-    for (int lat = 0; lat < 2; ++lat)
+    for (int g = 0; g < NGROUP; ++g)
         for (int k : act)
-            if ((b->slots[k].s->prm.lattice_hg == 5) == (lat == 1)) order.push_back(k);
-    // each lattice group is launched on its own sub-list of tiles, so a
-    // request's first tile is counted from the start of its group
+            if (group_of(b->slots[k].s) == g) order.push_back(k);
     int tile_total = 0;
     for (int k : order) {
         eulbfs_solver* h = b->slots[k].s;
         const int tx = (h->prm.nx + BATCH_TX - 1) / BATCH_TX, ty = (h->prm.ny + BATCH_TY - 1) / BATCH_TY;
         if (tile_total + tx * ty > b->tile_cap) return set_err(err, EULBFS_ENOMEM, "batch tile table full");
-        const int group = h->prm.lattice_hg == 5 ? 1 : 0;
+        const int group = group_of(h);
+        if (ntiles[group] == 0) first[group] = tile_total;
         BatchDesc<R>& D = hd[nd];
         D.P = h->dp;
         D.W[0] = state_at<R>(h->ws, h->L.W0, h->L);
@@ -794,14 +802,11 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     const BatchDesc<R>* dd = reinterpret_cast<const BatchDesc<R>*>(b->d_desc[par]);
     const StageCoef K[3] = {{0.0, 1.0, 1.0, 0}, {0.75, 0.25, 0.25, 0}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 1}};
     for (int64_t st = 0; st < s_eff; ++st)
-        for (int stage = 0; stage < 3; ++stage) {
-            if (ntiles[0])
-                HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par], ntiles[0], 9, K[stage], stage, b->grid_blocks,
-                                                b->stream));
-            if (ntiles[1])
-                HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + ntiles[0], ntiles[1], 5, K[stage], stage,
-                                                b->grid_blocks, b->stream));
-        }
+        for (int stage = 0; stage < 3; ++stage)
+            for (int g = 0; g < NGROUP; ++g)
+                if (ntiles[g])
+                    HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g], g >= 4 ? 5 : 9, g & 3,
+                                                    K[stage], stage, b->grid_blocks, b->stream));
     TickEvent te;
     HIP_TRY(hipEventCreateWithFlags(&te.ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(te.ev, b->stream));

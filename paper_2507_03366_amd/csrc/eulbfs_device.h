@@ -45,7 +45,17 @@ struct DevParams {
     double T_w[4];
     double wet[4];       // dx (4/xi) cos(theta): ghost C offset per mirror distance
     double inv_dt;
+    int fast;            // FAST_* fast paths valid for these constants
 };
+
+// Fast paths compiled as template flags.  Each gives the same values as the
+// general code, with fewer operations:
+//  FAST_HALF  delta_t = dx/2: the surrounding points with e_n = +-1, e_t = 0
+//             are the two cell centres, so no extrapolation along n is
+//             needed there and their density is the cell's.
+//  FAST_UCP   one heat capacity for all phases: every Eq. (7) mixture of C_p
+//             is that constant.
+enum { FAST_HALF = 1, FAST_UCP = 2 };
 
 // Pointers to one copy of the conserved vector W = (H, p, Mx, My, C).
 template <typename R>
@@ -292,11 +302,12 @@ __device__ __forceinline__ double chem_potential(const DevParams& P, double C, d
 template <typename R>
 struct Bases {
     R A[NPRIM], B[NPRIM], M[NPRIM], da[NPRIM], db[NPRIM], dm[NPRIM];
+    R rho_a, rho_b;  // cell densities (used by FAST_HALF)
 };
 
 // Bases of one variable from a plane of cell values: a and b are the two
 // cells (b = a + sn), sn the stride along n, st the stride along t.
-template <typename R>
+template <typename R, int FAST = 0>
 __device__ __forceinline__ void face_bases(const R* v, int a, int sn, int st, R c_sh, R c_h, R c_ds, R& A, R& B,
                                            R& M, R& da, R& db, R& dm)
 {
@@ -304,24 +315,30 @@ __device__ __forceinline__ void face_bases(const R* v, int a, int sn, int st, R 
     const R va = v[a], vb = v[b];
     const R ga = v[b] - v[a - sn];  // 2 dx dpsi_a/dn
     const R gb = v[b + sn] - va;    // 2 dx dpsi_b/dn
-    A = va + c_sh * ga;
-    B = vb - c_sh * gb;
+    if (FAST & FAST_HALF) {         // c_sh = 0
+        A = va;
+        B = vb;
+    } else {
+        A = va + c_sh * ga;
+        B = vb - c_sh * gb;
+    }
     M = R(0.5) * ((va + c_h * ga) + (vb - c_h * gb));
     da = c_ds * (v[a + st] - v[a - st]);
     db = c_ds * (v[b + st] - v[b - st]);
     dm = R(0.5) * (da + db);
 }
 
-template <typename R, int LAT>
+template <typename R, int LAT, int FAST = 0>
 __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X, R F[5])
 {
+    constexpr bool HALF = (FAST & FAST_HALF) != 0, UCP = (FAST & FAST_UCP) != 0;
     // old-level face state (text after Eq. 54) -> Eq. (7)
     const R Cf = clamp01(X.M[VC]);
     const R Fsf = clamp01(X.M[VFS]);
     const R rho_f = mix<R>(P.rho, Cf, Fsf);
     const R mu_f = mix<R>(P.mu, Cf, Fsf);
     const R lam_f = mix<R>(P.lam, Cf, Fsf);
-    const R cp_f = mix<R>(P.cp, Cf, Fsf);
+    const R cp_f = UCP ? R(P.cp[0]) : mix<R>(P.cp, Cf, Fsf);
 
     // point sums: group 0: e_n = +1, group 1: e_n = -1, group 2: e_n = 0
     R G[3] = {0, 0, 0}, Gt[3] = {0, 0, 0};  // sum w rho q, sum e_t w rho q
@@ -343,9 +360,11 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
             const R Fs = base[VFS] - R(et) * dd[VFS];
             const R un = base[VU] - R(et) * dd[VU];
             const R ut = base[VV] - R(et) * dd[VV];
+            // a cell centre (HALF, e_n = +-1, e_t = 0) has the cell's density
+            const bool centre = HALF && en != 0 && et == 0;
             const R Cc = clamp01(C);
             const R Fsc = clamp01(Fs);
-            const R rho = mix<R>(P.rho, Cc, Fsc);
+            const R rho = centre ? (g == 0 ? X.rho_a : X.rho_b) : mix<R>(P.rho, Cc, Fsc);
             const R eu = R(en) * un + R(et) * ut;
             const R uu = un * un + ut * ut;
             const R q = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
@@ -360,7 +379,7 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
                 if (en != 0 || et != 0) Ce[g] += wh * C * eu;
                 if (en != 0) {
                     const R T = base[VT] - R(et) * dd[VT];
-                    const R cp = mix<R>(P.cp, Cc, Fsc);
+                    const R cp = UCP ? R(P.cp[0]) : mix<R>(P.cp, Cc, Fsc);
                     Hq[g] += wh * cp * T * q;
                 }
             }

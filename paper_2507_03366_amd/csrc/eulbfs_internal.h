@@ -60,7 +60,7 @@ template <typename R>
 hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, int what, double* dst,
                          hipStream_t st);
 template <typename R>
-hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice,
+hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
                                 const StageCoef& K, int stage, int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,

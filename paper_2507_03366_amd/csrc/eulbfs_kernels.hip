@@ -87,7 +87,7 @@ struct FusedLds {
 
 // One tile of one stage: cells [i0, i0+TX) x [j0, j0+TY) of the grid described
 // by P.  Every thread of the workgroup must call it (it synchronises).
-template <typename R, int LAT, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY>
 __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& K, const State<R>& in,
                                            const State<R>& Wn, const State<R>& out, R* fsdot, int i0, int j0)
 {
@@ -146,8 +146,11 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             const int a = (fj + 2) * W2 + fi + 1;
 #pragma unroll
             for (int k = 0; k < NPRIM; ++k)
-                face_bases(sP[k], a, 1, W2, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k], X.dm[k]);
-            face_flux<R, LAT>(P, X, F);
+                face_bases<R, FAST>(sP[k], a, 1, W2, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
+                                    X.dm[k]);
+            X.rho_a = sP[NPRIM][a];
+            X.rho_b = sP[NPRIM][a + 1];
+            face_flux<R, LAT, FAST>(P, X, F);
             const int gi = i0 + fi;
             if (!P.periodic_x) {
                 if (gi == 0) wall_face(P, 0, F);
@@ -162,9 +165,12 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
 #pragma unroll
             for (int k = 0; k < NPRIM; ++k) {
                 const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
-                face_bases(sP[ks], a, W2, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k], X.dm[k]);
+                face_bases<R, FAST>(sP[ks], a, W2, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
+                                    X.dm[k]);
             }
-            face_flux<R, LAT>(P, X, F);
+            X.rho_a = sP[NPRIM][a];
+            X.rho_b = sP[NPRIM][a + W2];
+            face_flux<R, LAT, FAST>(P, X, F);
             const int gj = j0 + fj;
             if (!P.periodic_y) {
                 if (gj == 0) wall_face(P, 2, F);
@@ -209,7 +215,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
 // eight XCDs of the chip, each with its own L2; giving every XCD a
 // contiguous run of tiles keeps the halo rows a tile shares with its
 // neighbours in the same L2.
-template <typename R, int LAT, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_fused(DevParams P, StageCoef K, State<R> in, State<R> Wn, State<R> out, R* fsdot, int tiles_x,
                   int ntiles, int per_xcd)
@@ -217,13 +223,13 @@ __global__ void __launch_bounds__(TX* TY)
     const int b = blockIdx.x;
     const int t = (b % NXCD) * per_xcd + b / NXCD;
     if (t >= ntiles) return;
-    stage_tile<R, LAT, TX, TY>(P, K, in, Wn, out, fsdot, (t % tiles_x) * TX, (t / tiles_x) * TY);
+    stage_tile<R, LAT, FAST, TX, TY>(P, K, in, Wn, out, fsdot, (t % tiles_x) * TX, (t / tiles_x) * TY);
 }
 
 // One stage of every grid of a batch.  tile_req maps a tile of the
 // concatenated tile list to its request; workgroups loop over the tiles
 // (persistent grid), so one launch covers grids of any size mix.
-template <typename R, int LAT, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_batched(const BatchDesc<R>* __restrict__ descs, const int* __restrict__ tile_req, int ntiles,
                     StageCoef K, int stage)
@@ -233,7 +239,8 @@ __global__ void __launch_bounds__(TX* TY)
         const int lt = t - D.tile0;  // tile index within its request, 0 <= lt < tiles of the request
         const State<R>& in = D.W[stage];
         const State<R>& out = D.W[stage == 2 ? 0 : stage + 1];
-        stage_tile<R, LAT, TX, TY>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX, (lt / D.tiles_x) * TY);
+        stage_tile<R, LAT, FAST, TX, TY>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX,
+                                         (lt / D.tiles_x) * TY);
     }
 }
 
@@ -549,51 +556,83 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* part
 // ---------------------------------------------------------------------------
 static inline dim3 grid2(int nx, int ny, dim3 b) { return dim3((nx + b.x - 1) / b.x, (ny + b.y - 1) / b.y); }
 
-template <typename R, int LAT, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY>
 static hipError_t launch_fused_t(const DevParams& P, const StageCoef& K, const State<R>& in, const State<R>& Wn,
                                  const State<R>& out, R* fsdot, hipStream_t st)
 {
     const int tiles_x = (P.nx + TX - 1) / TX, tiles_y = (P.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;
     const int per_xcd = (ntiles + NXCD - 1) / NXCD;
-    hipLaunchKernelGGL((k_stage_fused<R, LAT, TX, TY>), dim3(per_xcd * NXCD), dim3(TX * TY), 0, st, P, K, in, Wn,
-                       out, fsdot, tiles_x, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_stage_fused<R, LAT, FAST, TX, TY>), dim3(per_xcd * NXCD), dim3(TX * TY), 0, st, P, K, in,
+                       Wn, out, fsdot, tiles_x, ntiles, per_xcd);
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice,
-                                const StageCoef& K, int stage, int grid, hipStream_t st)
+template <typename R, int LAT, int FAST>
+static hipError_t launch_fused_f(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,
+                                 const State<R>& Wn, const State<R>& out, R* fsdot, hipStream_t st)
 {
-    if (ntiles <= 0) return hipSuccess;
-    const int g = std::min(grid, ntiles);
-    if (lattice == 5)
-        hipLaunchKernelGGL((k_stage_batched<R, 5, BATCH_TX, BATCH_TY>), dim3(g), dim3(BATCH_TX * BATCH_TY), 0, st,
-                           descs, tile_req, ntiles, K, stage);
-    else
-        hipLaunchKernelGGL((k_stage_batched<R, 9, BATCH_TX, BATCH_TY>), dim3(g), dim3(BATCH_TX * BATCH_TY), 0, st,
-                           descs, tile_req, ntiles, K, stage);
-    return hipGetLastError();
+    switch (tile) {
+        case TILE_16x16: return launch_fused_t<R, LAT, FAST, 16, 16>(P, K, in, Wn, out, fsdot, st);
+        case TILE_64x8: return launch_fused_t<R, LAT, FAST, 64, 8>(P, K, in, Wn, out, fsdot, st);
+        case TILE_64x4: return launch_fused_t<R, LAT, FAST, 64, 4>(P, K, in, Wn, out, fsdot, st);
+        default: return launch_fused_t<R, LAT, FAST, 32, 8>(P, K, in, Wn, out, fsdot, st);
+    }
+}
+
+template <typename R, int LAT>
+static hipError_t launch_fused_l(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,
+                                 const State<R>& Wn, const State<R>& out, R* fsdot, hipStream_t st)
+{
+    switch (P.fast & (FAST_HALF | FAST_UCP)) {
+        case FAST_HALF: return launch_fused_f<R, LAT, FAST_HALF>(P, tile, K, in, Wn, out, fsdot, st);
+        case FAST_UCP: return launch_fused_f<R, LAT, FAST_UCP>(P, tile, K, in, Wn, out, fsdot, st);
+        case FAST_HALF | FAST_UCP:
+            return launch_fused_f<R, LAT, FAST_HALF | FAST_UCP>(P, tile, K, in, Wn, out, fsdot, st);
+        default: return launch_fused_f<R, LAT, 0>(P, tile, K, in, Wn, out, fsdot, st);
+    }
 }
 
 template <typename R>
 hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,
                               const State<R>& Wn, const State<R>& out, R* fsdot, hipStream_t st)
 {
-    if (P.lattice_hg == 5) {
-        switch (tile) {
-            case TILE_64x4: return launch_fused_t<R, 5, 64, 4>(P, K, in, Wn, out, fsdot, st);
-            case TILE_16x16: return launch_fused_t<R, 5, 16, 16>(P, K, in, Wn, out, fsdot, st);
-            case TILE_64x8: return launch_fused_t<R, 5, 64, 8>(P, K, in, Wn, out, fsdot, st);
-            default: return launch_fused_t<R, 5, 32, 8>(P, K, in, Wn, out, fsdot, st);
-        }
+    if (P.lattice_hg == 5) return launch_fused_l<R, 5>(P, tile, K, in, Wn, out, fsdot, st);
+    return launch_fused_l<R, 9>(P, tile, K, in, Wn, out, fsdot, st);
+}
+
+template <typename R, int LAT, int FAST>
+static void launch_batched_t(const BatchDesc<R>* descs, const int* tile_req, int ntiles, const StageCoef& K,
+                             int stage, int g, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, BATCH_TX, BATCH_TY>), dim3(g), dim3(BATCH_TX * BATCH_TY), 0,
+                       st, descs, tile_req, ntiles, K, stage);
+}
+
+// Requests of one batched launch share the lattice and the fast-path flags.
+template <typename R>
+hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
+                                const StageCoef& K, int stage, int grid, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int g = std::min(grid, ntiles);
+    const int f = fast & (FAST_HALF | FAST_UCP);
+#define EULBFS_BATCHED(LATV)                                                                                    \
+    switch (f) {                                                                                                \
+        case FAST_HALF: launch_batched_t<R, LATV, FAST_HALF>(descs, tile_req, ntiles, K, stage, g, st); break;   \
+        case FAST_UCP: launch_batched_t<R, LATV, FAST_UCP>(descs, tile_req, ntiles, K, stage, g, st); break;     \
+        case FAST_HALF | FAST_UCP:                                                                              \
+            launch_batched_t<R, LATV, FAST_HALF | FAST_UCP>(descs, tile_req, ntiles, K, stage, g, st);           \
+            break;                                                                                              \
+        default: launch_batched_t<R, LATV, 0>(descs, tile_req, ntiles, K, stage, g, st); break;                  \
     }
-    switch (tile) {
-        case TILE_64x4: return launch_fused_t<R, 9, 64, 4>(P, K, in, Wn, out, fsdot, st);
-        case TILE_16x16: return launch_fused_t<R, 9, 16, 16>(P, K, in, Wn, out, fsdot, st);
-        case TILE_64x8: return launch_fused_t<R, 9, 64, 8>(P, K, in, Wn, out, fsdot, st);
-        default: return launch_fused_t<R, 9, 32, 8>(P, K, in, Wn, out, fsdot, st);
+    if (lattice == 5) {
+        EULBFS_BATCHED(5)
+    } else {
+        EULBFS_BATCHED(9)
     }
+#undef EULBFS_BATCHED
+    return hipGetLastError();
 }
 
 template <typename R>
@@ -668,8 +707,8 @@ hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial,
                                                 hipStream_t);                                                      \
     template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
     template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);   \
-    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, const StageCoef&, int,  \
-                                                int, hipStream_t);
+    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, const StageCoef&,  \
+                                                int, int, hipStream_t);
 
 EULBFS_INSTANTIATE(double)
 EULBFS_INSTANTIATE(float)
