@@ -38,7 +38,9 @@ FLOP_PER_CELL_STAGE = {0: 1764.0, 1: 1598.0}
 # HBM bytes per k_stage_fused launch from FETCH_SIZE (x2.0) and WRITE_SIZE
 # (x1.0, factors from a 1 GiB device copy), valid only for the kernel sources
 # with this fingerprint (sha256 of csrc/eulbfs_device.h + csrc/eulbfs_kernels.hip)
-TRAFFIC = {"fingerprint": None, 0: None, 1: None}
+# Keys: "<kernel>/<precision>/<tile>"; the figure is HBM bytes per launch (one
+# RK stage) of the 512 x 512 workload.
+TRAFFIC = {"fingerprint": None}
 # compulsory HBM words per cell and time step (SSP-RK3 over the five conserved
 # planes and the dF_s/dt plane): stage 1 reads W^n and dF_s/dt and writes W1
 # (11), stage 2 reads W1, W^n, dF_s/dt and writes W2 (16), stage 3 reads W2,
@@ -115,11 +117,12 @@ def cpu_baseline(pr, st, budget_s: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=192)
+    ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--workload", default="C4")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--kernel", default="fused", choices=["fused", "split"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "split"],
+                    help="auto: the library times every tile shape of the fused kernel at create")
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -152,10 +155,11 @@ def main():
         return
     pr, st, desc = workload(args.workload)
     precision = 0 if args.precision == "fp64" else 1
-    kernel = E.KERNEL_FUSED if args.kernel == "fused" else E.KERNEL_SPLIT
+    kernel = {"auto": E.KERNEL_AUTO, "fused": E.KERNEL_FUSED, "split": E.KERNEL_SPLIT}[args.kernel]
     tile = tuple(int(v) for v in args.tile.split("x"))
     stream = torch.cuda.current_stream()
     s = E.Solver(pr, st, precision=precision, kernel=kernel, tile=tile, stream=stream)
+    sched = s.schedule()
     s.step(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -172,16 +176,20 @@ def main():
 
     cells = pr.cells
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
-    stage_launches = 3 * args.steps  # one fused launch per RK stage (split: four kernels per stage)
-    avg_launch_us = ms * 1e3 / stage_launches
+    # one launch of the dominant kernel per RK stage (split: four kernels per stage)
+    kname = "k_stage_fused" if sched[0] == E.KERNEL_FUSED else "split stage (4 kernels)"
+    launches = 3 * args.steps
+    avg_launch_us = ms * 1e3 / launches
     bpcs = bytes_per_cell_step(precision)
     alg_bytes_per_launch = bpcs * cells / 3.0
     hbm_gbs = alg_bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
     flop_per_launch = FLOP_PER_CELL_STAGE[precision] * cells
     tflops = flop_per_launch / (avg_launch_us * 1e-6) / 1e12
     fp = kernel_fingerprint()
-    traffic = TRAFFIC[precision] if (TRAFFIC["fingerprint"] == fp and kernel == E.KERNEL_FUSED
-                                     and args.workload == "C4") else None
+    tkey = f"{kname}/{args.precision}/{sched[1]}x{sched[2]}"
+    traffic = None
+    if TRAFFIC["fingerprint"] == fp and args.workload == "C4" and tkey in TRAFFIC:
+        traffic = TRAFFIC[tkey]
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -196,13 +204,15 @@ def main():
         "dtype": "f64" if precision == 0 else "f32 (H, C in f64)",
         "data": "synthetic",
         "config": {"workload": desc, "nx": pr.nx, "ny": pr.ny, "precision": args.precision,
-                   "kernel": args.kernel, "tile": args.tile, "steps_are": "SSP-RK3 time steps"},
+                   "kernel": args.kernel, "tile": args.tile, "steps_are": "SSP-RK3 time steps",
+                   "schedule": {"kernel": {0: "fused", 1: "split"}[sched[0]],
+                                "tile": f"{sched[1]}x{sched[2]}"}},
         # the binding roof is the vector ALU: the method's ~15 flop per HBM byte
         # is above the FP64 ridge of MI355X; the HBM view is given beside it
         "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS[precision],
                      "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS[precision], 4),
                      "traffic": traffic,
-                     "kernel": "k_stage_fused" if kernel == E.KERNEL_FUSED else "split stage (4 kernels)",
+                     "kernel": kname,
                      "avg_launch_us": round(avg_launch_us, 2),
                      "flop_per_cell_stage": FLOP_PER_CELL_STAGE[precision],
                      "alg_flop_per_launch": int(flop_per_launch),

@@ -64,6 +64,9 @@ extern "C" {
 
 #define EULBFS_KERNEL_FUSED 0 /* one fused flux + update kernel per RK stage      */
 #define EULBFS_KERNEL_SPLIT 1 /* ghost fill, primitives, face fluxes, update apart */
+#define EULBFS_KERNEL_AUTO 2  /* FUSED with the tile shape that create timed
+                                 fastest on the initial state (cached per
+                                 process for the grid, precision and lattice) */
 
 /* One side of the domain.  Sides are indexed 0: x-, 1: x+, 2: y-, 3: y+.
  * periodic must agree on opposite sides.  For a wall:
@@ -107,7 +110,8 @@ typedef struct {
     int32_t nx, ny;       /* cells; >= 4 each                            */
     int32_t lattice_hg;   /* 9 (paper) or 5: lattice of h and g          */
     int32_t precision;    /* EULBFS_FP64 or EULBFS_FP32                  */
-    int32_t kernel;       /* EULBFS_KERNEL_FUSED or EULBFS_KERNEL_SPLIT  */
+    int32_t kernel;       /* EULBFS_KERNEL_*: FUSED (any tile) and AUTO
+                             give the same bits, SPLIT agrees to rounding */
     int32_t surf_model;   /* 0: F_surf = -C grad mu_c (Sec. 2.4)
                              1: F_surf = -F_l C grad mu_c (Sec. 3.5)     */
     double dx;            /* cell size                                   */
@@ -120,7 +124,8 @@ typedef struct {
     double mobility, Qg;  /* M_c and Q_g of Eq. (41): tau_g = 1/2 + M_c/(Q_g delta_t) */
     double gx, gy;        /* gravity; G = rho g in Eq. (51)              */
     eulbfs_bc bc[4];
-    int32_t tile_x, tile_y; /* fused-kernel tile; 0 picks the default    */
+    int32_t tile_x, tile_y; /* fused-kernel tile (32x8, 64x4, 16x16, 64x8);
+                               0 picks 32x8; AUTO ignores it             */
     int32_t reserved[6];
 } eulbfs_params;
 
@@ -200,6 +205,13 @@ int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_de
 
 /* Release a solver; NULL is accepted. */
 int eulbfs_destroy(eulbfs_t h);
+
+/* The schedule a solver steps with: kernel is EULBFS_KERNEL_FUSED or _SPLIT
+ * (AUTO resolves to FUSED), tile_x x tile_y the fused kernel's tile (the one
+ * EULBFS_KERNEL_AUTO picked; 0 x 0 for the split kernels).  Any output
+ * pointer may be NULL.  Host call, no device work.  Returns EULBFS_EINVAL for
+ * a NULL handle. */
+int eulbfs_schedule(eulbfs_t h, int32_t* kernel, int32_t* tile_x, int32_t* tile_y);
 
 /* Text of the last failure on this handle (or, for h == NULL, of the last
  * failure of a create or host-only call on this thread). */

@@ -5,8 +5,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/eulbfs.h"
@@ -49,7 +53,8 @@ std::string check(const eulbfs_params* p)
     if (!(p->dt > 0)) return "dt must be > 0";
     if (p->lattice_hg != 5 && p->lattice_hg != 9) return "lattice_hg must be 5 or 9";
     if (p->precision != EULBFS_FP64 && p->precision != EULBFS_FP32) return "unknown precision";
-    if (p->kernel != EULBFS_KERNEL_FUSED && p->kernel != EULBFS_KERNEL_SPLIT) return "unknown kernel variant";
+    if (p->kernel != EULBFS_KERNEL_FUSED && p->kernel != EULBFS_KERNEL_SPLIT && p->kernel != EULBFS_KERNEL_AUTO)
+        return "unknown kernel variant";
     if (p->surf_model != 0 && p->surf_model != 1) return "surf_model must be 0 or 1";
     for (int k = 0; k < 3; ++k) {
         if (!(p->rho[k] > 0)) return "densities must be > 0";
@@ -262,6 +267,7 @@ struct eulbfs_solver {
     char* ws = nullptr;
     bool own_ws = false;
     int tile = TILE_32x8;
+    int sched = EULBFS_KERNEL_FUSED;  // FUSED or SPLIT (AUTO resolves to FUSED with a tuned tile)
     int64_t steps = 0;
     bool poisoned = false;
     std::string err;
@@ -283,7 +289,7 @@ int enqueue_raw(eulbfs_solver* h, int64_t n)
     R* fsdot = (R*)(h->ws + L.fsdot);
     const StageCoef K1{0.0, 1.0, 1.0, 0}, K2{0.75, 0.25, 0.25, 0}, K3{1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 1};
     for (int64_t s = 0; s < n; ++s) {
-        if (h->prm.kernel == EULBFS_KERNEL_SPLIT) {
+        if (h->sched == EULBFS_KERNEL_SPLIT) {
             const SplitScratch<R> X = split_at<R>(h->ws, L);
             HIP_TRY(launch_stage_split<R>(P, X, K1, W0, W0, WA, fsdot, nullptr, 0, h->stream));
             HIP_TRY(launch_stage_split<R>(P, X, K2, WA, W0, WB, fsdot, nullptr, 0, h->stream));
@@ -485,6 +491,88 @@ int do_residual(eulbfs_solver* h, double* Rout, double* Fx, double* Fy, int on_d
     return EULBFS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tile autotuner.
+//
+// EULBFS_KERNEL_AUTO times the fused stage kernel with every tile shape for a
+// few steps on the solver's own initial state, keeps the fastest and
+// initialises the state again.  The tile shape does not change any cell's
+// arithmetic, so the choice only changes the speed.  Choices are cached per
+// process by grid size, precision, lattice, fast-path flags and periodicity.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int nx, ny, precision, lattice, fast, px, py;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(nx, ny, precision, lattice, fast, px, py) <
+               std::tie(o.nx, o.ny, o.precision, o.lattice, o.fast, o.px, o.py);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;  // -> tile
+
+template <typename R>
+int autotune(eulbfs_solver* h, const eulbfs_init* init)
+{
+    std::string* err = &h->err;
+    const TuneKey key{h->prm.nx, h->prm.ny, h->prm.precision, h->prm.lattice_hg, h->dp.fast,
+                      h->dp.periodic_x, h->dp.periodic_y};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            h->tile = it->second;
+            return EULBFS_OK;
+        }
+    }
+    // about a millisecond of work per timing, at least two steps
+    const double cells = (double)h->prm.nx * h->prm.ny;
+    const int steps = (int)std::max(2.0, std::min(32.0, 4.0e6 / cells));
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return set_err(err, EULBFS_EDEVICE, "autotune: hipEventCreate failed");
+    }
+    int best = TILE_32x8, rc = EULBFS_OK;
+    float best_ms = 0.0f;
+    for (int tile = 0; tile < NTILES && rc == EULBFS_OK; ++tile) {
+        h->tile = tile;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && rc == EULBFS_OK; ++rep) {  // best of two
+            rc = enqueue_raw<R>(h, 1);
+            float t = 0.0f;
+            if (rc == EULBFS_OK &&
+                (hipEventRecord(a, h->stream) != hipSuccess || enqueue_raw<R>(h, steps) != EULBFS_OK ||
+                 hipEventRecord(b, h->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                 hipEventElapsedTime(&t, a, b) != hipSuccess))
+                rc = set_err(err, EULBFS_EDEVICE, "autotune: a timed launch failed");
+            if (rc == EULBFS_OK && (rep == 0 || t < ms)) ms = t;
+        }
+        if (rc == EULBFS_OK && (tile == 0 || ms < best_ms)) {
+            best = tile;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != EULBFS_OK) return rc;
+    h->tile = best;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = best;
+    }
+    return do_init<R>(h, init);  // the timed steps advanced the state
+}
+
+template <typename R>
+int setup_schedule(eulbfs_solver* h, const eulbfs_init* init)
+{
+    h->sched = h->prm.kernel == EULBFS_KERNEL_SPLIT ? EULBFS_KERNEL_SPLIT : EULBFS_KERNEL_FUSED;
+    if (h->prm.kernel == EULBFS_KERNEL_AUTO) return autotune<R>(h, init);
+    return EULBFS_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -539,6 +627,8 @@ int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
         h->own_ws = true;
     }
     int rc = prm->precision == EULBFS_FP32 ? do_init<float>(h, init) : do_init<double>(h, init);
+    if (rc == EULBFS_OK)
+        rc = prm->precision == EULBFS_FP32 ? setup_schedule<float>(h, init) : setup_schedule<double>(h, init);
     if (rc != EULBFS_OK) {
         g_thread_err = h->err;
         eulbfs_destroy(h);
@@ -617,6 +707,17 @@ int eulbfs_destroy(eulbfs_t h)
     if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     delete h;
+    return EULBFS_OK;
+}
+
+int eulbfs_schedule(eulbfs_t h, int32_t* kernel, int32_t* tile_x, int32_t* tile_y)
+{
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    static const int TX[NTILES] = {32, 64, 16, 64}, TY[NTILES] = {8, 4, 16, 8};
+    const bool split = h->sched == EULBFS_KERNEL_SPLIT;
+    if (kernel) *kernel = h->sched;
+    if (tile_x) *tile_x = split ? 0 : TX[h->tile];
+    if (tile_y) *tile_y = split ? 0 : TY[h->tile];
     return EULBFS_OK;
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libeulbfs.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
-KERNEL_FUSED, KERNEL_SPLIT = 0, 1
+KERNEL_FUSED, KERNEL_SPLIT, KERNEL_AUTO = 0, 1, 2
 INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
 ABI_VERSION = 1
 FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
@@ -79,6 +79,7 @@ def lib():
         L.eulbfs_set_field.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
         L.eulbfs_residual.argtypes = [vp, dp, dp, dp, ct.c_int32]
         L.eulbfs_destroy.argtypes = [vp]
+        L.eulbfs_schedule.argtypes = [vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.eulbfs_last_error.argtypes = [vp]
         L.eulbfs_last_error.restype = ct.c_char_p
         for f in ("eulbfs_check_params", "eulbfs_create", "eulbfs_step", "eulbfs_run", "eulbfs_query",
@@ -197,6 +198,13 @@ def eulbfs_residual(h, nx: int, ny: int):
     return R, Fx, Fy
 
 
+def eulbfs_schedule(h):
+    """(kernel, tile_x, tile_y) the solver steps with."""
+    k, tx, ty = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _raise(lib().eulbfs_schedule(h, ct.byref(k), ct.byref(tx), ct.byref(ty)), h)
+    return k.value, tx.value, ty.value
+
+
 def eulbfs_destroy(h) -> None:
     lib().eulbfs_destroy(h)
 
@@ -258,6 +266,10 @@ class Solver:
 
     def residual(self):
         return eulbfs_residual(self.h, self.nx, self.ny)
+
+    def schedule(self):
+        """(kernel, tile_x, tile_y) in use (the tile is what KERNEL_AUTO picked)."""
+        return eulbfs_schedule(self.h)
 
     def set_conserved(self, w6: np.ndarray):
         eulbfs_set_field(self.h, FIELD["W_ALL"], w6)

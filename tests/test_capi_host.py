@@ -91,6 +91,22 @@ def test_bad_tile_rejected():
     assert "tile" in E.eulbfs_check_params(P)
 
 
+def test_kernel_variants():
+    for k in (E.KERNEL_FUSED, E.KERNEL_SPLIT, E.KERNEL_AUTO):
+        P = _params()
+        P.kernel = k
+        assert E.eulbfs_check_params(P) == ""
+    P = _params()
+    P.kernel = 3
+    assert "kernel" in E.eulbfs_check_params(P)
+
+
+def test_schedule_query_rejects_null_handle():
+    with pytest.raises(E.EulbfsError) as ei:
+        E.eulbfs_schedule(None)
+    assert ei.value.code == E.EINVAL
+
+
 def test_create_rejects_before_touching_the_device():
     P = _params(delta_t=1.0)
     with pytest.raises(E.EulbfsError) as ei:
