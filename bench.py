@@ -27,20 +27,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s (MLUPS) & % HBM BW; batched solves/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# vector peaks of MI355X (256 CUs, 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3
-# TFLOP/s counts packed FP32, which this build keeps off, so unpacked FP32
-# issues at the FP64 rate
-VALU_PEAK_TFLOPS = {0: 78.6, 1: 157.3}
-# Floating-point operations per cell and RK stage executed by k_stage_fused,
-# counted with rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64/F32, 64 lanes
-# per wave instruction, FMA = 2) on the 512 x 512 droplet; see profiles/.
-FLOP_PER_CELL_STAGE = {0: 1764.0, 1: 1598.0}
-# HBM bytes per k_stage_fused launch from FETCH_SIZE (x2.0) and WRITE_SIZE
-# (x1.0, factors from a 1 GiB device copy), valid only for the kernel sources
-# with this fingerprint (sha256 of csrc/eulbfs_device.h + csrc/eulbfs_kernels.hip)
-# Keys: "<kernel>/<precision>/<tile>"; the figure is HBM bytes per launch (one
-# RK stage) of the 512 x 512 workload.
-TRAFFIC = {"fingerprint": None}
+# Published vector peaks of MI355X (256 CUs at 2.4 GHz): FP64 78.6 TFLOP/s,
+# FP32 157.3 TFLOP/s.  The FP32 figure assumes packed FP32 issue; the kernels
+# are built with packed FP32 off, so for them it is an upper bound.
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# Floating-point operations per cell and RK stage executed by k_stage_fused
+# with the 64 x 8 tile on the 512 x 512 droplet, counted with rocprofv3
+# (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 / _F32, 64 lanes per wave
+# instruction, FMA = 2; profiles/k_stage_fused_droplet512.md).  The FP32 mode
+# still does the closure, the H and C combination and mu_c in FP64.
+FLOP_PER_CELL_STAGE = {0: {"f64": 1481.3}, 1: {"f32": 1323.0, "f64": 134.2}}
+# HBM bytes per k_stage_fused launch (one RK stage) of the 512 x 512 droplet:
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch; the factors make a
+# 1 GiB device copy read and write 1 GiB), valid only for the kernel sources
+# with this fingerprint (sha256 of csrc/eulbfs_device.h + csrc/eulbfs_kernels.hip).
+# Keys: "<kernel>/<precision>/<tile>".
+TRAFFIC = {
+    "fingerprint": "88d05121eed699aa",
+    "k_stage_fused/fp64/32x8": 31882342, "k_stage_fused/fp64/64x4": 31883162,
+    "k_stage_fused/fp64/16x16": 31856538, "k_stage_fused/fp64/64x8": 31866982,
+    "k_stage_fused/fp32/32x8": 21815808, "k_stage_fused/fp32/64x4": 21803520,
+    "k_stage_fused/fp32/16x16": 21814477, "k_stage_fused/fp32/64x8": 21816013,
+}
+
+
+def flop_peak(precision: int):
+    """Counted flop per cell and stage, and the peak for that mix of FP32 and
+    FP64 operations (time at peak of each part, summed)."""
+    mix = FLOP_PER_CELL_STAGE[precision]
+    flop = sum(mix.values())
+    return flop, flop / sum(v / VALU_PEAK_TFLOPS[k] for k, v in mix.items())
+
+
 # compulsory HBM words per cell and time step (SSP-RK3 over the five conserved
 # planes and the dF_s/dt plane): stage 1 reads W^n and dF_s/dt and writes W1
 # (11), stage 2 reads W1, W^n, dF_s/dt and writes W2 (16), stage 3 reads W2,
@@ -183,7 +201,8 @@ def main():
     bpcs = bytes_per_cell_step(precision)
     alg_bytes_per_launch = bpcs * cells / 3.0
     hbm_gbs = alg_bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
-    flop_per_launch = FLOP_PER_CELL_STAGE[precision] * cells
+    flop_cell, peak_tflops = flop_peak(precision)
+    flop_per_launch = flop_cell * cells
     tflops = flop_per_launch / (avg_launch_us * 1e-6) / 1e12
     fp = kernel_fingerprint()
     tkey = f"{kname}/{args.precision}/{sched[1]}x{sched[2]}"
@@ -209,12 +228,13 @@ def main():
                                 "tile": f"{sched[1]}x{sched[2]}"}},
         # the binding roof is the vector ALU: the method's ~15 flop per HBM byte
         # is above the FP64 ridge of MI355X; the HBM view is given beside it
-        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS[precision],
-                     "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS[precision], 4),
+        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": round(peak_tflops, 1),
+                     "unit": "TFLOP/s", "frac": round(tflops / peak_tflops, 4),
                      "traffic": traffic,
                      "kernel": kname,
                      "avg_launch_us": round(avg_launch_us, 2),
                      "flop_per_cell_stage": FLOP_PER_CELL_STAGE[precision],
+                     "tile": f"{sched[1]}x{sched[2]}",
                      "alg_flop_per_launch": int(flop_per_launch),
                      "kernel_fingerprint": fp,
                      "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
