@@ -48,11 +48,14 @@ struct DevParams {
     int fast;            // FAST_* fast paths valid for these constants
 };
 
-// Fast paths compiled as template flags.  Each gives the same values as the
-// general code, with fewer operations:
+// Fast paths compiled as template flags.  Each computes the same quantities
+// as the general code (equal up to rounding order), with fewer operations:
 //  FAST_HALF  delta_t = dx/2: the surrounding points with e_n = +-1, e_t = 0
 //             are the two cell centres, so no extrapolation along n is
-//             needed there and their density is the cell's.
+//             needed there and their density is the cell's; the face value
+//             is 5/8 (psi_a + psi_b) - 1/8 (psi_a-1 + psi_b+1), and the
+//             tangential differences are kept unscaled with their factor
+//             (1/4, or 1/8 for the face group) folded into the coefficients.
 //  FAST_UCP   one heat capacity for all phases: every Eq. (7) mixture of C_p
 //             is that constant.
 enum { FAST_HALF = 1, FAST_UCP = 2 };
@@ -288,7 +291,8 @@ __device__ __forceinline__ double chem_potential(const DevParams& P, double C, d
 //   B = psi_b - (dx/2 - delta_t) dpsi_b/dn        (group e_n = -1)
 //   M = average of both extrapolations to x_f     (group e_n = 0; also the
 //                                                  old-level face value)
-//   d = delta_t dpsi/dt of the group's cell (the mean for the face group).
+//   d = delta_t dpsi/dt of the group's cell (the mean for the face group;
+//       FAST_HALF keeps 4 d for the cells and 8 d for the face group).
 // With a_X = tau_X - 1/2 each star distribution is
 //   X* = (1 - a_X) X^eq(x_f) + a_X X^eq(x_f - e delta_t),
 // so each flux is (1 - a_X) times a moment of the face equilibrium (closed
@@ -313,15 +317,19 @@ __device__ __forceinline__ void face_bases(const R* v, int a, int sn, int st, R 
 {
     const int b = a + sn;
     const R va = v[a], vb = v[b];
-    const R ga = v[b] - v[a - sn];  // 2 dx dpsi_a/dn
-    const R gb = v[b + sn] - va;    // 2 dx dpsi_b/dn
-    if (FAST & FAST_HALF) {         // c_sh = 0
+    if (FAST & FAST_HALF) {  // c_sh = 0, c_h = c_ds = 1/4; d kept unscaled
         A = va;
         B = vb;
-    } else {
-        A = va + c_sh * ga;
-        B = vb - c_sh * gb;
+        M = R(0.625) * (va + vb) - R(0.125) * (v[a - sn] + v[b + sn]);
+        da = v[a + st] - v[a - st];
+        db = v[b + st] - v[b - st];
+        dm = da + db;
+        return;
     }
+    const R ga = v[b] - v[a - sn];  // 2 dx dpsi_a/dn
+    const R gb = v[b + sn] - va;    // 2 dx dpsi_b/dn
+    A = va + c_sh * ga;
+    B = vb - c_sh * gb;
     M = R(0.5) * ((va + c_h * ga) + (vb - c_h * gb));
     da = c_ds * (v[a + st] - v[a - st]);
     db = c_ds * (v[b + st] - v[b - st]);
@@ -350,22 +358,27 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
         const int en = g == 0 ? 1 : (g == 1 ? -1 : 0);
         const R* base = g == 0 ? X.A : (g == 1 ? X.B : X.M);
         const R* dd = g == 0 ? X.da : (g == 1 ? X.db : X.dm);
+        const double dsc = !HALF ? 1.0 : (g == 2 ? 0.125 : 0.25);  // scale of the stored d
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int et = k == 0 ? 0 : (k == 1 ? 1 : -1);
+            const R ets = R(et * dsc);
             const R w9 = en == 0 ? (et == 0 ? R(4.0 / 9.0) : R(1.0 / 9.0)) : (et == 0 ? R(1.0 / 9.0) : R(1.0 / 36.0));
             const bool in_hg = LAT == 9 || en == 0 || et == 0;
             const R wh = LAT == 9 ? w9 : (en == 0 && et == 0 ? R(1.0 / 3.0) : R(1.0 / 6.0));
-            const R C = base[VC] - R(et) * dd[VC];
-            const R Fs = base[VFS] - R(et) * dd[VFS];
-            const R un = base[VU] - R(et) * dd[VU];
-            const R ut = base[VV] - R(et) * dd[VV];
+            // e_t = 0: the base itself (0 * d is not folded away in IEEE arithmetic)
+            const R C = et == 0 ? base[VC] : base[VC] - ets * dd[VC];
+            const R Fs = et == 0 ? base[VFS] : base[VFS] - ets * dd[VFS];
+            const R un = et == 0 ? base[VU] : base[VU] - ets * dd[VU];
+            const R ut = et == 0 ? base[VV] : base[VV] - ets * dd[VV];
             // a cell centre (HALF, e_n = +-1, e_t = 0) has the cell's density
             const bool centre = HALF && en != 0 && et == 0;
             const R Cc = clamp01(C);
             const R Fsc = clamp01(Fs);
             const R rho = centre ? (g == 0 ? X.rho_a : X.rho_b) : mix<R>(P.rho, Cc, Fsc);
-            const R eu = R(en) * un + R(et) * ut;
+            const R eun = en == 0 ? R(0) : (en > 0 ? un : -un);
+            const R eut = et == 0 ? R(0) : (et > 0 ? ut : -ut);
+            const R eu = en == 0 ? eut : (et == 0 ? eun : eun + eut);
             const R uu = un * un + ut * ut;
             const R q = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
             const R rq = rho * q;
@@ -378,7 +391,7 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
             if (in_hg) {
                 if (en != 0 || et != 0) Ce[g] += wh * C * eu;
                 if (en != 0) {
-                    const R T = base[VT] - R(et) * dd[VT];
+                    const R T = et == 0 ? base[VT] : base[VT] - ets * dd[VT];
                     const R cp = UCP ? R(P.cp[0]) : mix<R>(P.cp, Cc, Fsc);
                     Hq[g] += wh * cp * T * q;
                 }
@@ -389,13 +402,15 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
     // Eq. (56): new face state from the point equilibria f^eq (Eq. 29) and g^eq (Eq. 42)
     const R p_f = sixth * (X.A[VP] + X.B[VP]) + R(2.0 / 3.0) * X.M[VP] + third * (G[0] + G[1] + G[2]);
     const R m_n = sixth * (X.A[VP] - X.B[VP]) + third * (G[0] - G[1]);
-    const R m_t = -R(1.0 / 18.0) * (X.da[VP] + X.db[VP]) - R(2.0 / 9.0) * X.dm[VP] + third * (Gt[0] + Gt[1] + Gt[2]);
+    // with FAST_HALF dm = da + db unscaled: 1/18 (da + db) / 4 + 2/9 dm / 8 = dm / 24
+    const R m_t = (HALF ? -R(1.0 / 24.0) * X.dm[VP] : -R(1.0 / 18.0) * (X.da[VP] + X.db[VP]) - R(2.0 / 9.0) * X.dm[VP]) +
+                  third * (Gt[0] + Gt[1] + Gt[2]);
     const R Q = R(P.muQ);
     const R C_new = X.M[VC] + R(3) * Q * (sixth * (X.A[VMU] + X.B[VMU]) - third * X.M[VMU]) +
                     R(3) * (Ce[0] + Ce[1] + Ce[2]);
     // point moments of the star distributions (f^eq-m with the face density, Eq. 33)
     const R SMn = sixth * (X.A[VP] + X.B[VP]) + third * rho_f * (Qs[0] + Qs[1]);
-    const R SMt = R(1.0 / 18.0) * (X.db[VP] - X.da[VP]) + third * rho_f * (Qt[0] - Qt[1]);
+    const R SMt = R(HALF ? 1.0 / 72.0 : 1.0 / 18.0) * (X.db[VP] - X.da[VP]) + third * rho_f * (Qt[0] - Qt[1]);
     const R SH = R(P.cpref) * sixth * (X.A[VT] - X.B[VT]) + (Hq[0] - Hq[1]);
     const R SG = R(3) * Q * sixth * (X.A[VMU] - X.B[VMU]) + R(3) * (Ce[0] - Ce[1]);
 
