@@ -135,9 +135,13 @@ DevParams make_dev(const eulbfs_params* p)
     d.gx = p->gx;
     d.gy = p->gy;
     d.expansion = 1.0 - p->rho[0] / p->rho[1];
-    // fast paths give the same bits as the generic face arithmetic
+    // compile-time fast paths valid for these constants (same quantities up to rounding)
     d.fast = (0.5 * p->dx - p->delta_t == 0.0 ? FAST_HALF : 0) |
              (p->cp[0] == p->cp[1] && p->cp[1] == p->cp[2] ? FAST_UCP : 0);
+    d.Hs_u = p->cp[0] * p->T_s;
+    d.Hl_u = p->cp[0] * p->T_l + p->latent;
+    d.inv_cp = 1.0 / p->cp[0];
+    d.inv_dH = d.Hl_u - d.Hs_u > 1e-300 ? 1.0 / (d.Hl_u - d.Hs_u) : 0.0;
     return d;
 }
 

@@ -46,6 +46,9 @@ struct DevParams {
     double wet[4];       // dx (4/xi) cos(theta): ghost C offset per mirror distance
     double inv_dt;
     int fast;            // FAST_* fast paths valid for these constants
+    // FAST_UCP closure constants: H_s = C_p T_s, H_l = C_p T_l + L, 1/C_p,
+    // 1/(H_l - H_s) (0 without a mushy range)
+    double Hs_u, Hl_u, inv_cp, inv_dH;
 };
 
 // Fast paths compiled as template flags.  Each computes the same quantities
@@ -57,7 +60,8 @@ struct DevParams {
 //             tangential differences are kept unscaled with their factor
 //             (1/4, or 1/8 for the face group) folded into the coefficients.
 //  FAST_UCP   one heat capacity for all phases: every Eq. (7) mixture of C_p
-//             is that constant.
+//             is that constant, and the closure's H_s, H_l and reciprocals
+//             are constants of the run.
 enum { FAST_HALF = 1, FAST_UCP = 2 };
 
 // Pointers to one copy of the conserved vector W = (H, p, Mx, My, C).
@@ -104,8 +108,22 @@ __device__ __forceinline__ R mix(const double g[3], R C, R Fs)
 
 // Eqs. (5)-(6) with H = C_p T + L F_l and the condensed-phase mixtures
 // C_p^S = Eq.7(C, F_s = C), C_p^L = Eq.7(C, F_s = 0).  Cc is C clamped to [0,1].
+template <int FAST = 0>
 __device__ __forceinline__ void closure(const DevParams& P, double H, double Cc, double& Fl, double& T)
 {
+    if (FAST & FAST_UCP) {  // one C_p: H_s, H_l and the reciprocals are constants
+        if (H < P.Hs_u) {
+            Fl = 0.0;
+            T = P.T_s + (H - P.Hs_u) * P.inv_cp;
+        } else if (H > P.Hl_u) {
+            Fl = 1.0;
+            T = P.T_l + (H - P.Hl_u) * P.inv_cp;
+        } else {
+            Fl = P.inv_dH > 0.0 ? (H - P.Hs_u) * P.inv_dH : 1.0;
+            T = P.T_s + Fl * (P.T_l - P.T_s);
+        }
+        return;
+    }
     const double cpS = mix<double>(P.cp, Cc, Cc);
     const double cpL = mix<double>(P.cp, Cc, 0.0);
     const double Hs = cpS * P.T_s;
@@ -123,11 +141,12 @@ __device__ __forceinline__ void closure(const DevParams& P, double H, double Cc,
     }
 }
 
+template <int FAST = 0>
 __device__ __forceinline__ double solid_fraction(const DevParams& P, double H, double C)
 {
     const double Cc = clamp01(C);
     double Fl, T;
-    closure(P, H, Cc, Fl, T);
+    closure<FAST>(P, H, Cc, Fl, T);
     return Cc * (1.0 - Fl);
 }
 
@@ -248,12 +267,12 @@ __device__ __forceinline__ Cons<R> load_bc(const DevParams& P, const State<R>& S
 enum { VT = 0, VC, VFS, VU, VV, VP, VMU, NPRIM };  // + rho stored after
 
 // Closure, Eq. (7) density and velocity of one cell (mu_c done separately).
-template <typename R>
+template <typename R, int FAST = 0>
 __device__ __forceinline__ void primitives(const DevParams& P, const Cons<R>& w, R out[NPRIM + 1])
 {
     const double Cc = clamp01(w.C);
     double Fl, T;
-    closure(P, w.H, Cc, Fl, T);
+    closure<FAST>(P, w.H, Cc, Fl, T);
     const R Fs = R(Cc * (1.0 - Fl));
     const R rho = mix<R>(P.rho, R(Cc), Fs);
     const R inv = R(3) * rcp(rho);  // 1 / (rho c_s^2)
@@ -439,13 +458,13 @@ __device__ __forceinline__ void wall_face(const DevParams& P, int side, R F[5])
 
 // Source vector F_E of Eq. (51) (with the C source in row 5) at one cell.
 // c: the cell's primitives (with rho at NPRIM), dux.. central differences.
-template <typename R>
+template <typename R, int FAST = 0>
 __device__ __forceinline__ void sources(const DevParams& P, const R c[NPRIM + 1], R Fl, R fsdot, R dudx,
                                         R dvdy, R drhodx, R drhody, R dmudx, R dmudy, R S[5])
 {
     const R rho = c[NPRIM];
     const R u = c[VU], v = c[VV], C = c[VC];
-    const R cp = mix<R>(P.cp, clamp01(C), c[VFS]);
+    const R cp = (FAST & FAST_UCP) ? R(P.cp[0]) : mix<R>(P.cp, clamp01(C), c[VFS]);
     const R ex = R(P.expansion);
     const R surf = P.surf_model == 1 ? -Fl * C : -C;
     S[0] = cp * c[VT] * (dudx + dvdy);

@@ -24,7 +24,7 @@ namespace eulbfs {
 // ---------------------------------------------------------------------------
 // Per-cell update shared by the fused and the split stage kernels.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int FAST = 0>
 __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef& K, const R c[NPRIM + 1],
                                             const Cons<R>& Wk, R dudx, R dvdy, R drhodx, R drhody, R dmudx,
                                             R dmudy, const R dF[5], const State<R>& Wn, const State<R>& out,
@@ -33,12 +33,12 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     R Fl = R(0);
     if (P.surf_model == 1) {
         double fl, T;
-        closure(P, Wk.H, clamp01(Wk.C), fl, T);
+        closure<FAST>(P, Wk.H, clamp01(Wk.C), fl, T);
         Fl = R(fl);
     }
     const R fsd = fsdot[q];
     R S[5];
-    sources(P, c, Fl, fsd, dudx, dvdy, drhodx, drhody, dmudx, dmudy, S);
+    sources<R, FAST>(P, c, Fl, fsd, dudx, dvdy, drhodx, drhody, dmudx, dmudy, S);
     R res[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) res[k] = -dF[k] + S[k];
@@ -57,7 +57,7 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     R mynew = ca * wn.my + cb * Wk.my + cdtr * res[3];
     const double Cnew = K.ca * wn.C + K.cb * Wk.C + cdt * (double)res[4];
     // rigid solid: M <- (1 - F_s) M with F_s of the new stage value
-    const double Fs_new = solid_fraction(P, Hnew, Cnew);
+    const double Fs_new = solid_fraction<FAST>(P, Hnew, Cnew);
     mxnew *= R(1.0 - Fs_new);
     mynew *= R(1.0 - Fs_new);
     out.H[q] = Hnew;
@@ -65,7 +65,7 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     out.mx[q] = mxnew;
     out.my[q] = mynew;
     out.C[q] = Cnew;
-    if (K.last) fsdot[q] = R((Fs_new - solid_fraction(P, wn.H, wn.C)) * P.inv_dt);
+    if (K.last) fsdot[q] = R((Fs_new - solid_fraction<FAST>(P, wn.H, wn.C)) * P.inv_dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,7 +127,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
         w.my = sW[2 * W3 * H3 + q3];
         w.C = sC[q3];
         R pr[NPRIM + 1];
-        primitives(P, w, pr);
+        primitives<R, FAST>(P, w, pr);
         pr[VMU] = R(chem_potential(P, w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3], sC[q3 - W3]));
 #pragma unroll
         for (int k = 0; k <= NPRIM; ++k) sP[k][q] = pr[k];
@@ -208,7 +208,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     const R dmy = (sP[VMU][c2 + W2] - sP[VMU][c2 - W2]) * i2dx;
     const size_t q = (size_t)j * P.pitch + i;
     const Cons<R> wk = read_cell(in, P.pitch, i, j);
-    cell_update(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, (R*)nullptr, 0, q);
+    cell_update<R, FAST>(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, (R*)nullptr, 0, q);
 }
 
 // One stage of one grid.  Workgroups are dispatched round-robin over the
