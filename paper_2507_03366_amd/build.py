@@ -18,6 +18,10 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # compiler-generated packed FP32 arithmetic is kept off on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression: every kernel
+    # variant (tile shape, face passes, batched) rounds a cell's arithmetic
+    # the same way, whatever the surrounding code
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 
