@@ -40,7 +40,8 @@ FLOP_PER_CELL_STAGE = {0: {"f64": 1481.3}, 1: {"f32": 1323.0, "f64": 134.2}}
 # HBM bytes per k_stage_fused launch (one RK stage) of the 512 x 512 droplet:
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch; the factors make a
 # 1 GiB device copy read and write 1 GiB), valid only for the kernel sources
-# with this fingerprint (sha256 of csrc/eulbfs_device.h + csrc/eulbfs_kernels.hip).
+# with this fingerprint (sha256 of csrc/eulbfs_device.h, csrc/eulbfs_kernels.hip
+# and build.py).
 # Keys: "<kernel>/<precision>/<tile>".
 TRAFFIC = {
     "fingerprint": "88d05121eed699aa",
@@ -78,8 +79,8 @@ def kernel_fingerprint() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("eulbfs_device.h", "eulbfs_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_2507_03366_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/eulbfs_device.h", "csrc/eulbfs_kernels.hip", "build.py"):  # sources and compile flags
+        with open(os.path.join(ROOT, "paper_2507_03366_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -124,8 +124,8 @@ typedef struct {
     double mobility, Qg;  /* M_c and Q_g of Eq. (41): tau_g = 1/2 + M_c/(Q_g delta_t) */
     double gx, gy;        /* gravity; G = rho g in Eq. (51)              */
     eulbfs_bc bc[4];
-    int32_t tile_x, tile_y; /* fused-kernel tile (32x8, 64x4, 16x16, 64x8);
-                               0 picks 32x8; AUTO ignores it             */
+    int32_t tile_x, tile_y; /* fused-kernel tile (32x8, 64x4, 16x16, 64x8,
+                               32x16); 0 picks 32x8; AUTO ignores it     */
     int32_t reserved[6];
 } eulbfs_params;
 

@@ -576,6 +576,7 @@ static hipError_t launch_fused_f(const DevParams& P, int tile, const StageCoef& 
         case TILE_16x16: return launch_fused_t<R, LAT, FAST, 16, 16>(P, K, in, Wn, out, fsdot, st);
         case TILE_64x8: return launch_fused_t<R, LAT, FAST, 64, 8>(P, K, in, Wn, out, fsdot, st);
         case TILE_64x4: return launch_fused_t<R, LAT, FAST, 64, 4>(P, K, in, Wn, out, fsdot, st);
+        case TILE_32x16: return launch_fused_t<R, LAT, FAST, 32, 16>(P, K, in, Wn, out, fsdot, st);
         default: return launch_fused_t<R, LAT, FAST, 32, 8>(P, K, in, Wn, out, fsdot, st);
     }
 }
