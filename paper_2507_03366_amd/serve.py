@@ -11,7 +11,8 @@ as its fixed step budget is done.  It reports solves per second and the
 p50/p99 time from arrival to result.
 
 The one-at-a-time baseline runs the same requests in FP64, each on its own
-solver (create, run, read the diagnostics, destroy), in arrival order.
+solver (create with the autotuned tile, run, read the diagnostics, destroy),
+in arrival order.
 """
 from __future__ import annotations
 
@@ -163,7 +164,7 @@ def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None)
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
-        s = E.Solver(pr, st, precision=precision, stream=stream)
+        s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream)
         try:
             s.step(r.nsteps)
             d = s.diagnostics()
