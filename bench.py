@@ -31,33 +31,43 @@ HBM_PEAK_GBS = 8000.0
 # FP32 157.3 TFLOP/s.  The FP32 figure assumes packed FP32 issue; the kernels
 # are built with packed FP32 off, so for them it is an upper bound.
 VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-# Floating-point operations per cell and RK stage executed by k_stage_fused
-# with the 64 x 8 tile on the 512 x 512 droplet, counted with rocprofv3
-# (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 / _F32, 64 lanes per wave
-# instruction, FMA = 2; profiles/k_stage_fused_droplet512.md).  The FP32 mode
-# still does the closure, the H and C combination and mu_c in FP64.
-FLOP_PER_CELL_STAGE = {0: {"f64": 1481.3}, 1: {"f32": 1323.0, "f64": 134.2}}
-# HBM bytes per k_stage_fused launch (one RK stage) of the 512 x 512 droplet:
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch; the factors make a
-# 1 GiB device copy read and write 1 GiB), valid only for the kernel sources
-# with this fingerprint (sha256 of csrc/eulbfs_device.h, csrc/eulbfs_kernels.hip
-# and build.py).
-# Keys: "<kernel>/<precision>/<tile>".
-TRAFFIC = {
-    "fingerprint": "88d05121eed699aa",
-    "k_stage_fused/fp64/32x8": 31882342, "k_stage_fused/fp64/64x4": 31883162,
-    "k_stage_fused/fp64/16x16": 31856538, "k_stage_fused/fp64/64x8": 31866982,
-    "k_stage_fused/fp32/32x8": 21815808, "k_stage_fused/fp32/64x4": 21803520,
-    "k_stage_fused/fp32/16x16": 21814477, "k_stage_fused/fp32/64x8": 21816013,
+# Per tile shape of k_stage_fused on the 512 x 512 droplet, counted with
+# rocprofv3 (profiles/k_stage_fused_droplet512.md):
+#   f64 / f32  floating-point operations per cell and RK stage executed
+#              (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 / _F32, 64 lanes per
+#              wave instruction, FMA = 2; they include the tile's recomputed
+#              halo of primitives and faces); the FP32 mode still does the
+#              closure, the H and C combination and mu_c in FP64
+#   valu       VALU lane-instructions per cell and stage (SQ_INSTS_VALU x 64)
+#   hbm        HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB
+#              per dispatch; the factors make a 1 GiB device copy read and
+#              write 1 GiB)
+# valid only for the sources and compile flags with this fingerprint (sha256
+# of csrc/eulbfs_device.h, csrc/eulbfs_kernels.hip and build.py).
+COUNTS_FINGERPRINT = "1f821726792481db"
+COUNTS = {
+    "fp64/32x8": {"f64": 1239.8, "valu": 1293.1, "hbm": 31856538},
+    "fp64/64x4": {"f64": 1365.1, "valu": 1441.0, "hbm": 31860429},
+    "fp64/16x16": {"f64": 1239.6, "valu": 1279.3, "hbm": 31865549},
+    "fp64/64x8": {"f64": 1182.9, "valu": 1251.6, "hbm": 31855104},
+    "fp64/32x16": {"f64": 1125.0, "valu": 1176.4, "hbm": 31854694},
+    "fp32/32x8": {"f32": 1152.6, "f64": 78.1, "valu": 1275.4, "hbm": 21792870},
+    "fp32/64x4": {"f32": 1260.3, "f64": 91.3, "valu": 1419.4, "hbm": 21799629},
+    "fp32/16x16": {"f32": 1152.6, "f64": 77.8, "valu": 1259.4, "hbm": 21798912},
+    "fp32/64x8": {"f32": 1098.8, "f64": 76.1, "valu": 1221.4, "hbm": 21795328},
+    "fp32/32x16": {"f32": 1046.1, "f64": 72.0, "valu": 1151.4, "hbm": 21780173},
 }
+# every VALU instruction of a wave64 occupies a 16-lane SIMD for 4 cycles:
+# 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second at most
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
-def flop_peak(precision: int):
+def flop_peak(mix: dict):
     """Counted flop per cell and stage, and the peak for that mix of FP32 and
     FP64 operations (time at peak of each part, summed)."""
-    mix = FLOP_PER_CELL_STAGE[precision]
-    flop = sum(mix.values())
-    return flop, flop / sum(v / VALU_PEAK_TFLOPS[k] for k, v in mix.items())
+    parts = {k: v for k, v in mix.items() if k in VALU_PEAK_TFLOPS}
+    flop = sum(parts.values())
+    return flop, flop / sum(v / VALU_PEAK_TFLOPS[k] for k, v in parts.items())
 
 
 # compulsory HBM words per cell and time step (SSP-RK3 over the five conserved
@@ -176,7 +186,8 @@ def main():
     precision = 0 if args.precision == "fp64" else 1
     kernel = {"auto": E.KERNEL_AUTO, "fused": E.KERNEL_FUSED, "split": E.KERNEL_SPLIT}[args.kernel]
     tile = tuple(int(v) for v in args.tile.split("x"))
-    stream = torch.cuda.current_stream()
+    # a created stream: the solver captures its steps into a HIP graph and replays it
+    stream = torch.cuda.Stream()
     s = E.Solver(pr, st, precision=precision, kernel=kernel, tile=tile, stream=stream)
     sched = s.schedule()
     s.step(args.warmup)
@@ -202,14 +213,17 @@ def main():
     bpcs = bytes_per_cell_step(precision)
     alg_bytes_per_launch = bpcs * cells / 3.0
     hbm_gbs = alg_bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
-    flop_cell, peak_tflops = flop_peak(precision)
-    flop_per_launch = flop_cell * cells
-    tflops = flop_per_launch / (avg_launch_us * 1e-6) / 1e12
     fp = kernel_fingerprint()
-    tkey = f"{kname}/{args.precision}/{sched[1]}x{sched[2]}"
-    traffic = None
-    if TRAFFIC["fingerprint"] == fp and args.workload == "C4" and tkey in TRAFFIC:
-        traffic = TRAFFIC[tkey]
+    ckey = f"{args.precision}/{sched[1]}x{sched[2]}"
+    counts = COUNTS.get(ckey) if (fp == COUNTS_FINGERPRINT and sched[0] == E.KERNEL_FUSED) else None
+    if counts:
+        flop_cell, peak_tflops = flop_peak(counts)
+        flop_per_launch = flop_cell * cells
+        tflops = flop_per_launch / (avg_launch_us * 1e-6) / 1e12
+        issue = counts["valu"] / 64 * cells / (avg_launch_us * 1e-6) / VALU_ISSUE_PEAK
+    else:  # the counters were taken on other kernel sources or another kernel
+        flop_cell = peak_tflops = flop_per_launch = tflops = issue = None
+    traffic = counts["hbm"] if (counts and args.workload == "C4") else None
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -227,16 +241,17 @@ def main():
                    "kernel": args.kernel, "tile": args.tile, "steps_are": "SSP-RK3 time steps",
                    "schedule": {"kernel": {0: "fused", 1: "split"}[sched[0]],
                                 "tile": f"{sched[1]}x{sched[2]}"}},
-        # the binding roof is the vector ALU: the method's ~15 flop per HBM byte
-        # is above the FP64 ridge of MI355X; the HBM view is given beside it
-        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": round(peak_tflops, 1),
-                     "unit": "TFLOP/s", "frac": round(tflops / peak_tflops, 4),
-                     "traffic": traffic,
-                     "kernel": kname,
-                     "avg_launch_us": round(avg_launch_us, 2),
-                     "flop_per_cell_stage": FLOP_PER_CELL_STAGE[precision],
-                     "tile": f"{sched[1]}x{sched[2]}",
-                     "alg_flop_per_launch": int(flop_per_launch),
+        # the binding roof is the vector ALU: the kernel's ~10 counted FP64 flop
+        # per compulsory HBM byte sits at the FP64 ridge (78.6 TFLOP/s over
+        # 8 TB/s = 9.8), and every VALU instruction, FP64 or not, holds its
+        # SIMD for 4 cycles; the HBM view is given beside it
+        "roofline": {"bound": "alu", "achieved": tflops and round(tflops, 2),
+                     "peak": peak_tflops and round(peak_tflops, 1), "unit": "TFLOP/s",
+                     "frac": tflops and round(tflops / peak_tflops, 4), "traffic": traffic,
+                     "kernel": kname, "tile": f"{sched[1]}x{sched[2]}", "avg_launch_us": round(avg_launch_us, 2),
+                     "flop_per_cell_stage": counts and {k: v for k, v in counts.items() if k in VALU_PEAK_TFLOPS},
+                     "alg_flop_per_launch": flop_per_launch and int(flop_per_launch),
+                     "valu_issue_frac": issue and round(issue, 4),
                      "kernel_fingerprint": fp,
                      "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
