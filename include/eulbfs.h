@@ -47,7 +47,7 @@ extern "C" {
 #define EULBFS_EINVAL (-1)    /* bad argument or parameter                        */
 #define EULBFS_ENOMEM (-2)    /* workspace too small or allocation failed         */
 #define EULBFS_EDEVICE (-3)   /* a HIP call failed                                */
-#define EULBFS_EUNSTABLE (-4) /* NaN/Inf in the state; the handle stays poisoned  */
+#define EULBFS_EUNSTABLE (-4) /* NaN/Inf or a speed above c_s; handle poisoned    */
 #define EULBFS_EBUSY (-5)     /* no free slot / HBM budget (batch API)            */
 #define EULBFS_ENOTSUP (-6)   /* valid request this build does not provide        */
 
@@ -186,7 +186,9 @@ typedef struct eulbfs_solver* eulbfs_t;
 int eulbfs_step(eulbfs_t h, int64_t nsteps);
 
 /* eulbfs_step, then synchronise the stream and check the state: returns
- * EULBFS_EUNSTABLE (and poisons the handle) if any cell is non-finite. */
+ * EULBFS_EUNSTABLE (and poisons the handle) if any cell is non-finite or any
+ * speed |u| exceeds the lattice sound speed c_s = 1/sqrt(3) (the flux
+ * reconstruction assumes low Mach number). */
 int eulbfs_run(eulbfs_t h, int64_t nsteps);
 
 /* Read a field (EULBFS_FIELD_*) or the diagnostics (EULBFS_SCALAR_DIAG) into

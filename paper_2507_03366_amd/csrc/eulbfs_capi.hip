@@ -341,7 +341,9 @@ int enqueue_steps(eulbfs_solver* h, int64_t n)
 {
     std::string* err = &h->err;
     int64_t left = n;
-    if (n >= 2 * GRAPH_STEPS && ensure_graph<R>(h)) {
+    // the graph is captured at the first call (capture launches nothing), so
+    // later calls, timed ones included, find it ready
+    if (ensure_graph<R>(h)) {
         for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS) HIP_TRY(hipGraphLaunch(h->graph_exec, h->stream));
     }
     const int rc = enqueue_raw<R>(h, left);
@@ -661,6 +663,12 @@ int eulbfs_run(eulbfs_t h, int64_t nsteps)
     if (d[5] != 0.0 || !std::isfinite(d[0]) || !std::isfinite(d[2])) {
         h->poisoned = true;
         return set_err(&h->err, EULBFS_EUNSTABLE, "non-finite values in the state after step " + std::to_string(h->steps));
+    }
+    if (!(d[4] <= 1.0 / std::sqrt(3.0))) {
+        h->poisoned = true;
+        return set_err(&h->err, EULBFS_EUNSTABLE,
+                       "speed " + std::to_string(d[4]) + " above the lattice sound speed after step " +
+                           std::to_string(h->steps));
     }
     return EULBFS_OK;
 }
@@ -1006,7 +1014,9 @@ int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision,
         eulbfs_batch_destroy(b);
         return set_err(err, EULBFS_EDEVICE, "batch set-up failed (pinned tables, events or device query)");
     }
-    b->grid_blocks = cus * (precision == EULBFS_FP32 ? 4 : 3);  // resident workgroups of the batched kernel
+    // the persistent grid: every resident workgroup of the batched kernel
+    const int per_cu = precision == EULBFS_FP32 ? batched_blocks_per_cu<float>() : batched_blocks_per_cu<double>();
+    b->grid_blocks = cus * std::max(per_cu, 1);
     *out = b;
     return EULBFS_OK;
 }

@@ -636,6 +636,26 @@ hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, 
     return hipGetLastError();
 }
 
+// Resident workgroups per CU of the batched stage kernel (the smallest over
+// its lattice and fast-path instantiations).
+template <typename R>
+int batched_blocks_per_cu()
+{
+    using Kernel = void (*)(const BatchDesc<R>*, const int*, int, StageCoef, int);
+    constexpr int TX = BATCH_TX, TY = BATCH_TY;
+    const Kernel ks[] = {k_stage_batched<R, 9, 0, TX, TY>, k_stage_batched<R, 9, 1, TX, TY>,
+                         k_stage_batched<R, 9, 2, TX, TY>, k_stage_batched<R, 9, 3, TX, TY>,
+                         k_stage_batched<R, 5, 0, TX, TY>, k_stage_batched<R, 5, 1, TX, TY>,
+                         k_stage_batched<R, 5, 2, TX, TY>, k_stage_batched<R, 5, 3, TX, TY>};
+    int n = 1 << 30;
+    for (Kernel k : ks) {
+        int m = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k, TX * TY, 0) != hipSuccess) return 0;
+        n = std::min(n, m);
+    }
+    return n;
+}
+
 template <typename R>
 hipError_t launch_stage_split(const DevParams& P, const SplitScratch<R>& X, const StageCoef& K, const State<R>& in,
                               const State<R>& Wn, const State<R>& out, R* fsdot, R* resid, size_t resid_stride,
@@ -709,7 +729,8 @@ hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial,
     template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
     template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);   \
     template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, const StageCoef&,  \
-                                                int, int, hipStream_t);
+                                                int, int, hipStream_t);                                            \
+    template int batched_blocks_per_cu<R>();
 
 EULBFS_INSTANTIATE(double)
 EULBFS_INSTANTIATE(float)

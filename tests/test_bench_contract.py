@@ -1,0 +1,41 @@
+"""bench.py keeps its output contract: one JSON line with the metric, the
+roofline and (on request) the serving and CPU-baseline objects; more than
+one GPU is refused with a message."""
+import json
+import pathlib
+import subprocess
+import sys
+
+import pytest
+
+ROOT = pathlib.Path(__file__).resolve().parent.parent
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+@pytest.mark.gpu
+def test_bench_json_line():
+    r = subprocess.run([sys.executable, "-u", str(ROOT / "bench.py"), "--steps", "3", "--warmup", "1",
+                        "--serving", "6", "--serving-steps", "20", "--cpu-budget", "1"],
+                       capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "serving", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 3 and d["value"] > 0
+    assert d["config"]["workload"].startswith("static droplet")
+    rl = d["roofline"]
+    assert rl["bound"] == "alu" and rl["avg_launch_us"] > 0 and 0 < rl["hbm"]["frac"] < 1
+    if rl["frac"] is not None:
+        assert 0 < rl["frac"] < 1 and 0 < rl["valu_issue_frac"] < 1
+    assert d["serving"]["batched_fp32_burst"]["failed"] == []
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0

@@ -253,6 +253,22 @@ def test_nonfinite_state_is_reported():
         s.close()
 
 
+def test_supersonic_state_is_reported():
+    # |u| = 0.8 > c_s = 1/sqrt(3): outside the low-Mach range of the flux reconstruction
+    pr, st = PB.conductive_freezing()
+    s = E.Solver(pr, st)
+    try:
+        w6 = s.conserved()
+        w6[2] = 0.8 / 3.0  # rho c_s^2 u with rho = 1
+        s.set_conserved(w6)
+        with pytest.raises(E.EulbfsError) as ei:
+            s.run(1)
+        assert ei.value.code == E.EUNSTABLE
+        assert "sound speed" in str(ei.value)
+    finally:
+        s.close()
+
+
 def test_conductive_freezing_neumann_on_gpu():
     """The full 20 000-step run of Sec. 3.1 (one-phase) on the GPU: the front
     is within 0.5 cell of 2 k sqrt(alpha t) (k(0.1) = 0.2200163)."""
