@@ -176,6 +176,19 @@ __device__ __forceinline__ double ghost_enthalpy(const DevParams& P, double T, d
     return enthalpy_of(P, T, Fl, C);
 }
 
+// Conserved state of the cell at linear index q = j * pitch + i.
+template <typename R>
+__device__ __forceinline__ Cons<R> read_at(const State<R>& S, size_t q)
+{
+    Cons<R> w;
+    w.H = S.H[q];
+    w.p = S.p[q];
+    w.mx = S.mx[q];
+    w.my = S.my[q];
+    w.C = S.C[q];
+    return w;
+}
+
 template <typename R>
 __device__ __forceinline__ Cons<R> read_cell(const State<R>& S, int pitch, int i, int j)
 {

@@ -48,7 +48,7 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
         return;
     }
     Cons<R> wn = Wk;
-    if (K.ca != 0.0) wn = read_cell(Wn, P.pitch, (int)(q % P.pitch), (int)(q / P.pitch));
+    if (K.ca != 0.0) wn = read_at(Wn, q);
     const double cdt = K.cc * P.dt;
     const double Hnew = K.ca * wn.H + K.cb * Wk.H + cdt * (double)res[0];
     const R ca = R(K.ca), cb = R(K.cb), cdtr = R(cdt);
@@ -104,15 +104,25 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     const int tid = threadIdx.x;
     __syncthreads();  // the LDS of a previous tile of this workgroup is free
 
-    // 1. stage W of the tile and three halo layers
-    for (int q = tid; q < W3 * H3; q += NT) {
-        const int li = q % W3, lj = q / W3;
-        const Cons<R> w = load_bc(P, in, i0 + li - NG, j0 + lj - NG);
+    // 1. stage W of the tile and three halo layers (boundary rules only for
+    // tiles whose halo leaves the grid)
+    auto stage = [&](int q, const Cons<R>& w) {
         sH[q] = w.H;
         sW[0 * W3 * H3 + q] = w.p;
         sW[1 * W3 * H3 + q] = w.mx;
         sW[2 * W3 * H3 + q] = w.my;
         sC[q] = w.C;
+    };
+    if (i0 >= NG && j0 >= NG && i0 + TX + NG <= P.nx && j0 + TY + NG <= P.ny) {
+        for (int q = tid; q < W3 * H3; q += NT) {
+            const int li = q % W3, lj = q / W3;
+            stage(q, read_cell(in, P.pitch, i0 + li - NG, j0 + lj - NG));
+        }
+    } else {
+        for (int q = tid; q < W3 * H3; q += NT) {
+            const int li = q % W3, lj = q / W3;
+            stage(q, load_bc(P, in, i0 + li - NG, j0 + lj - NG));
+        }
     }
     __syncthreads();
 
