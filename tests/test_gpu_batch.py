@@ -78,6 +78,32 @@ def test_batch_matches_oracle_and_is_independent_of_the_mix(oracle):
         assert np.array_equal(alone[0], mix[k]), k
 
 
+def test_batch_full_size_requests_match_oracle(oracle):
+    """Serving-mix grids at their full sizes: a 512 x 512 impact and a 256 x 256
+    static droplet in one FP64 batch, 10 steps against the oracle."""
+    reqs = [PB.impact_droplet(n=512, we=50.0, re=1000.0, ste=0.5, supercool=0.5, theta_deg=70.0),
+            PB.static_droplet(n=256, R=64, theta_deg=110.0, ste=0.3)]
+    reqs[1] = (reqs[1][0].replace(sigma=PB.static_droplet()[0].sigma), reqs[1][1])
+    out, diags = _run_batch(reqs, [10, 10], tick=5, budget=1 << 30)
+    oracle.set_threads(16)
+    for (pr, st), w, d in zip(reqs, out, diags):
+        assert d["steps"] == 10
+        Wref, _ = oracle.run(pr, st, 10)
+        errs = errors(w[:5], Wref)
+        assert max(errs.values()) < 1e-12, (pr.nx, errs)
+
+
+def test_empty_batch_tick_and_poll():
+    import torch
+
+    b = E.Batch(1 << 26, 4, precision=E.FP32, stream=torch.cuda.Stream())
+    try:
+        b.tick(10)  # nothing resident: no launch, no error
+        assert b.poll() == []
+    finally:
+        b.close()
+
+
 def test_batch_agrees_with_single_solver():
     pr, st = PB.static_droplet(n=64, R=16)
     pr = pr.replace(sigma=0.015625)

@@ -70,6 +70,13 @@ def _cases():
         "y-": _walls(PB.NOSLIP, PB.DIRICHLET, 70.0), "y+": _walls(PB.FREESLIP, PB.ADIABATIC, 100.0)}, **base)))
     cases.append(("mushy_dt", PB.Problem(nx=12, ny=9, T_s=-0.2, T_l=0.1, delta_t=0.3, periodic_y=True, walls={
         "x-": _walls(PB.NOSLIP, PB.DIRICHLET, 90.0), "x+": _walls(PB.NOSLIP, PB.ADIABATIC, 90.0)}, **base)))
+    # one heat capacity for all phases (the uniform-C_p fast path), with and
+    # without delta_t = dx/2, with a mushy range
+    ucp = dict(base, cp=(1.1, 1.1, 1.1))
+    cases.append(("ucp_dt_mushy", PB.Problem(nx=12, ny=9, T_s=-0.2, T_l=0.1, delta_t=0.3, periodic_y=True, walls={
+        "x-": _walls(PB.NOSLIP, PB.DIRICHLET, 80.0), "x+": _walls(PB.NOSLIP, PB.ADIABATIC, 90.0)}, **ucp)))
+    cases.append(("ucp_half_mushy", PB.Problem(nx=10, ny=11, T_s=-0.2, T_l=0.1, periodic_x=True, walls={
+        "y-": _walls(PB.NOSLIP, PB.DIRICHLET, 110.0), "y+": _walls(PB.FREESLIP, PB.ADIABATIC, 90.0)}, **ucp)))
     return cases
 
 
@@ -199,6 +206,16 @@ def test_droplet_full_size_512(oracle):
     configuration of the benchmark (fused kernel, tile picked by the autotuner)."""
     pr, st = PB.static_droplet()
     _parity_run(oracle, pr, st, 20, tol=1e-12, kernel=E.KERNEL_AUTO)
+
+
+def test_large_grid_2048(oracle):
+    """2048 x 2048 (16384 tiles of 32 x 8, 4096 of 32 x 16: every XCD holds many
+    tiles) in the autotuned configuration, two steps against the oracle."""
+    pr, _ = PB.static_droplet(n=2048, R=512)
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr)
+    st.C = PB.droplet_profile(X, Y, 1024.0, 0.0, 512.0, 4.0)
+    _parity_run(oracle, pr, st, 2, tol=1e-12, kernel=E.KERNEL_AUTO)
 
 
 def test_film_full_size_256(oracle):
