@@ -44,18 +44,18 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #              write 1 GiB)
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_kernels.hip and build.py).
-COUNTS_FINGERPRINT = "1d54e0f449c44e03"
+COUNTS_FINGERPRINT = "353a549ef39a8bef"
 COUNTS = {
-    "fp64/32x8": {"f64": 1239.8, "valu": 1293.1, "hbm": 31856538},
-    "fp64/64x4": {"f64": 1365.1, "valu": 1441.0, "hbm": 31860429},
-    "fp64/16x16": {"f64": 1239.6, "valu": 1279.3, "hbm": 31865549},
-    "fp64/64x8": {"f64": 1182.9, "valu": 1251.6, "hbm": 31855104},
-    "fp64/32x16": {"f64": 1125.0, "valu": 1176.4, "hbm": 31854694},
-    "fp32/32x8": {"f32": 1152.6, "f64": 78.1, "valu": 1275.4, "hbm": 21792870},
-    "fp32/64x4": {"f32": 1260.3, "f64": 91.3, "valu": 1419.4, "hbm": 21799629},
-    "fp32/16x16": {"f32": 1152.6, "f64": 77.8, "valu": 1259.4, "hbm": 21798912},
-    "fp32/64x8": {"f32": 1098.8, "f64": 76.1, "valu": 1221.4, "hbm": 21795328},
-    "fp32/32x16": {"f32": 1046.1, "f64": 72.0, "valu": 1151.4, "hbm": 21780173},
+    "fp64/32x8": {"f64": 1238.1, "valu": 1232.9, "hbm": 31856469},
+    "fp64/64x4": {"f64": 1363.6, "valu": 1382.1, "hbm": 31861973},
+    "fp64/16x16": {"f64": 1237.8, "valu": 1220.3, "hbm": 31861077},
+    "fp64/64x8": {"f64": 1181.5, "valu": 1200.5, "hbm": 31846229},
+    "fp64/32x16": {"f64": 1123.3, "valu": 1123.1, "hbm": 31861236},
+    "fp32/32x8": {"f32": 1147.9, "f64": 76.4, "valu": 1214.6, "hbm": 21794105},
+    "fp32/64x4": {"f32": 1256.0, "f64": 89.8, "valu": 1359.8, "hbm": 21796236},
+    "fp32/16x16": {"f32": 1147.7, "f64": 76.1, "valu": 1199.7, "hbm": 21792848},
+    "fp32/64x8": {"f32": 1094.6, "f64": 74.6, "valu": 1169.6, "hbm": 21793715},
+    "fp32/32x16": {"f32": 1041.5, "f64": 70.3, "valu": 1097.4, "hbm": 21794900},
 }
 # every VALU instruction of a wave64 occupies a 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second at most
