@@ -649,7 +649,7 @@ int eulbfs_step(eulbfs_t h, int64_t nsteps)
 {
     if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
     if (nsteps < 0) return set_err(&h->err, EULBFS_EINVAL, "nsteps must be >= 0");
-    if (h->poisoned) return set_err(&h->err, EULBFS_EUNSTABLE, "state is non-finite; restore a checkpoint");
+    if (h->poisoned) return set_err(&h->err, EULBFS_EUNSTABLE, "state is unstable (non-finite or supersonic); restore a checkpoint");
     return h->prm.precision == EULBFS_FP32 ? enqueue_steps<float>(h, nsteps) : enqueue_steps<double>(h, nsteps);
 }
 
