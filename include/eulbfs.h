@@ -202,7 +202,9 @@ int eulbfs_set_field(eulbfs_t h, int32_t what, const void* in, size_t bytes, int
 /* Evaluate the residual R(W) of Eq. (57) for the current state with the
  * split kernels: R (5 planes nx*ny), Fx (5 planes (nx+1)*ny, face i at
  * x = i dx), Fy (5 planes nx*(ny+1), face j at y = j dx); any may be NULL.
- * Doubles, host memory unless on_device.  Synchronises. */
+ * Doubles, host memory unless on_device.  A diagnostic call: it allocates
+ * temporary device scratch (freed before it returns) unless the solver was
+ * created with EULBFS_KERNEL_SPLIT, whose workspace holds it.  Synchronises. */
 int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device);
 
 /* Release a solver; NULL is accepted. */
