@@ -263,6 +263,8 @@ hipError_t to_double(const R* src, size_t spitch, int w, int h, double* dst, hip
 
 // Steps per captured graph of a single solver.
 constexpr int GRAPH_STEPS = 8;
+// Ticks a batch enqueues ahead of the device before eulbfs_batch_tick waits.
+constexpr int MAX_INFLIGHT = 2;
 
 struct eulbfs_solver {
     eulbfs_params prm;
@@ -352,8 +354,11 @@ int enqueue_steps(eulbfs_solver* h, int64_t n)
     return EULBFS_OK;
 }
 
+// Initial state from six planes.  With sync = false nothing waits: host planes
+// must stay valid until the stream has run the copy (batch admission passes
+// planes already on the device).
 template <typename R>
-int do_init(eulbfs_solver* h, const eulbfs_init* init)
+int do_init(eulbfs_solver* h, const eulbfs_init* init, bool sync = true)
 {
     std::string* err = &h->err;
     const Layout& L = h->L;
@@ -370,8 +375,24 @@ int do_init(eulbfs_solver* h, const eulbfs_init* init)
         HIP_TRY(launch_init<R>(h->dp, src, W0, fsdot, h->stream));
     else
         HIP_TRY(launch_set_conserved<R>(h->dp, src, W0, fsdot, -1, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (sync) HIP_TRY(hipStreamSynchronize(h->stream));
     return EULBFS_OK;
+}
+
+// The EULBFS_SCALAR_DIAG record from the raw reduction sums.
+void diag_from_sums(const eulbfs_solver* h, const double r[NRED], double* out)
+{
+    const double dV = h->prm.dx * h->prm.dx;
+    out[0] = r[0] * dV;
+    out[1] = r[1] * dV;
+    out[2] = r[2] * dV;
+    out[3] = r[3] * dV;
+    out[4] = r[4];
+    out[5] = r[5];
+    out[6] = r[6] * h->prm.dx;
+    out[7] = (double)h->steps * h->prm.dt;
+    out[8] = (double)h->steps;
+    out[9] = h->prm.dt;
 }
 
 template <typename R>
@@ -386,17 +407,7 @@ int do_diag(eulbfs_solver* h, double* host_out)
     double r[NRED];
     HIP_TRY(hipMemcpyAsync(r, dout, sizeof r, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    const double dV = h->prm.dx * h->prm.dx;
-    host_out[0] = r[0] * dV;
-    host_out[1] = r[1] * dV;
-    host_out[2] = r[2] * dV;
-    host_out[3] = r[3] * dV;
-    host_out[4] = r[4];
-    host_out[5] = r[5];
-    host_out[6] = r[6] * h->prm.dx;
-    host_out[7] = (double)h->steps * h->prm.dt;
-    host_out[8] = (double)h->steps;
-    host_out[9] = h->prm.dt;
+    diag_from_sums(h, r, host_out);
     return EULBFS_OK;
 }
 
@@ -603,8 +614,13 @@ size_t eulbfs_workspace_bytes(const eulbfs_params* prm)
     return make_layout(prm).total;
 }
 
-int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes, void* hip_stream,
-                  eulbfs_solver** out)
+}  // extern "C"
+
+namespace {
+
+// eulbfs_create; with sync = false the initial state is only enqueued.
+int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes, void* hip_stream,
+                  bool sync, eulbfs_solver** out)
 {
     std::string* err = nullptr;
     if (!out) return set_err(err, EULBFS_EINVAL, "out is NULL");
@@ -633,7 +649,7 @@ int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
         }
         h->own_ws = true;
     }
-    int rc = prm->precision == EULBFS_FP32 ? do_init<float>(h, init) : do_init<double>(h, init);
+    int rc = prm->precision == EULBFS_FP32 ? do_init<float>(h, init, sync) : do_init<double>(h, init, sync);
     if (rc == EULBFS_OK)
         rc = prm->precision == EULBFS_FP32 ? setup_schedule<float>(h, init) : setup_schedule<double>(h, init);
     if (rc != EULBFS_OK) {
@@ -643,6 +659,27 @@ int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
     }
     *out = h;
     return EULBFS_OK;
+}
+
+// Release a solver's host state; sync = false when no enqueued work can
+// still touch its workspace.
+void free_solver(eulbfs_solver* h, bool sync)
+{
+    if (sync && (h->stream || h->ws)) (void)hipStreamSynchronize(h->stream);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eulbfs_create(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes, void* hip_stream,
+                  eulbfs_solver** out)
+{
+    return create_solver(prm, init, d_ws, ws_bytes, hip_stream, true, out);
 }
 
 int eulbfs_step(eulbfs_t h, int64_t nsteps)
@@ -714,12 +751,7 @@ int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_de
 
 int eulbfs_destroy(eulbfs_t h)
 {
-    if (!h) return EULBFS_OK;
-    if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
-    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    if (h->own_ws && h->ws) (void)hipFree(h->ws);
-    delete h;
+    if (h) free_solver(h, true);
     return EULBFS_OK;
 }
 
@@ -792,6 +824,14 @@ struct eulbfs_batch {
     int64_t tick = 0;
     std::vector<TickEvent> events;  // recent ticks
     int64_t completed_tick = 0;     // every tick < completed_tick has completed
+    // results and uploads that need no host wait: the reduction sums of each
+    // request, copied into pinned memory by the tick that finishes it; host
+    // initial planes staged in pinned memory and copied on an upload stream
+    double* h_sums = nullptr;  // max_slots x NRED
+    hipStream_t upload = nullptr;
+    double* h_stage = nullptr;
+    size_t stage_cap = 0;  // doubles
+    hipEvent_t stage_done = nullptr;
     std::string err;
 };
 
@@ -873,6 +913,12 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
         }
     }
     if (act.empty() || s_eff <= 0) return EULBFS_OK;
+    // at most MAX_INFLIGHT ticks enqueued ahead of the device
+    while ((int)b->events.size() >= MAX_INFLIGHT) {
+        const size_t before = b->events.size();
+        batch_progress(b, true);
+        if (b->events.size() == before) return set_err(err, EULBFS_EDEVICE, "waiting for a tick failed");
+    }
     const int par = b->parity;
     b->parity ^= 1;
     if (b->upload_done[par]) HIP_TRY(hipEventSynchronize(b->upload_done[par]));
@@ -921,6 +967,17 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
                 if (ntiles[g])
                     HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g], g >= 4 ? 5 : 9, g & 3,
                                                     K[stage], stage, b->grid_blocks, b->stream));
+    // requests finished by this tick: their FP64 sums go to pinned memory
+    for (int k : act) {
+        Slot& sl = b->slots[k];
+        if (sl.done + s_eff < sl.nsteps) continue;
+        eulbfs_solver* h = sl.s;
+        double* part = (double*)(h->ws + h->L.red_partial);
+        double* dout = (double*)(h->ws + h->L.red_out);
+        HIP_TRY(launch_reduce<R>(h->dp, state_at<R>(h->ws, h->L.W0, h->L), part, h->L.red_blocks, dout, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->h_sums + (size_t)k * NRED, dout, NRED * sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream));
+    }
     TickEvent te;
     HIP_TRY(hipEventCreateWithFlags(&te.ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(te.ev, b->stream));
@@ -934,6 +991,33 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     }
     ++b->tick;
     return EULBFS_OK;
+}
+
+// Copy n doubles of host planes to dst (device) through the batch's pinned
+// staging buffer on the upload stream; the batch stream waits for the copy.
+int admit_stage(eulbfs_batch* b, const double* src, size_t n, char* dst)
+{
+    std::string* err = &b->err;
+    HIP_TRY(hipEventSynchronize(b->stage_done));  // the previous upload has left the buffer
+    if (b->stage_cap < n) {
+        if (b->h_stage) HIP_TRY(hipHostFree(b->h_stage));
+        b->h_stage = nullptr;
+        b->stage_cap = 0;
+        HIP_TRY(hipHostMalloc((void**)&b->h_stage, n * sizeof(double), hipHostMallocDefault));
+        b->stage_cap = n;
+    }
+    std::memcpy(b->h_stage, src, n * sizeof(double));
+    HIP_TRY(hipMemcpyAsync(dst, b->h_stage, n * sizeof(double), hipMemcpyHostToDevice, b->upload));
+    HIP_TRY(hipEventRecord(b->stage_done, b->upload));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->stage_done, 0));
+    return EULBFS_OK;
+}
+
+// The request's last tick has completed: nothing enqueued touches it any more.
+bool slot_settled(eulbfs_batch* b, const Slot& sl)
+{
+    batch_progress(b, false);
+    return sl.done >= sl.nsteps && sl.finish_tick >= 0 && sl.finish_tick < b->completed_tick;
 }
 
 Slot* batch_slot(eulbfs_batch* b, int32_t slot)
@@ -1007,6 +1091,10 @@ int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision,
         ok &= hipHostMalloc((void**)&b->h_tiles[k], tiles_bytes, hipHostMallocDefault) == hipSuccess;
         ok &= hipEventCreateWithFlags(&b->upload_done[k], hipEventDisableTiming) == hipSuccess;
     }
+    ok = ok && hipHostMalloc((void**)&b->h_sums, (size_t)max_slots * NRED * sizeof(double), hipHostMallocDefault) ==
+                   hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&b->upload, hipStreamNonBlocking) == hipSuccess;  // default priority
+    ok = ok && hipEventCreateWithFlags(&b->stage_done, hipEventDisableTiming) == hipSuccess;
     int dev = 0, cus = 0;
     ok &= hipGetDevice(&dev) == hipSuccess;
     ok &= hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
@@ -1035,12 +1123,29 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
     int k = 0;
     while (k < b->max_slots && b->slots[k].s) ++k;
     if (k == b->max_slots) return set_err(err, EULBFS_EBUSY, "no free slot");
+    if (!init || !init->planes) return set_err(err, EULBFS_EINVAL, "init or init->planes is NULL");
     const eulbfs_params p = batch_view(prm);
-    const size_t bytes = align_up(make_layout(&p).total);
+    const Layout L = make_layout(&p);
+    const size_t bytes = align_up(L.total);
     const size_t off = arena_alloc(b, bytes);
     if (off == SIZE_MAX) return set_err(err, EULBFS_EBUSY, "not enough free arena for this request");
+    // Host planes go through pinned memory and the upload stream into the
+    // request's own staging area (its arena range is idle: a freed range is
+    // only reused once its last tick has completed), so admission does not
+    // wait for the ticks in flight; the batch stream waits for the copy.
+    eulbfs_init dinit = *init;
+    if (!init->on_device) {
+        const size_t n6 = (size_t)6 * p.nx * p.ny;
+        int rc = admit_stage(b, init->planes, n6, b->arena + off + L.staging);
+        if (rc != EULBFS_OK) {
+            arena_free(b, off, bytes);
+            return rc;
+        }
+        dinit.on_device = 1;
+        dinit.planes = (const double*)(b->arena + off + L.staging);
+    }
     eulbfs_solver* h = nullptr;
-    const int rc = eulbfs_create(&p, init, b->arena + off, bytes, b->stream, &h);
+    const int rc = create_solver(&p, &dinit, b->arena + off, bytes, b->stream, false, &h);
     if (rc != EULBFS_OK) {
         arena_free(b, off, bytes);
         return set_err(err, rc, g_thread_err);
@@ -1082,6 +1187,11 @@ int eulbfs_batch_query(eulbfs_batch_t b, int32_t slot, int32_t what, void* out, 
 {
     Slot* sl = batch_slot(b, slot);
     if (!sl) return set_err(b ? &b->err : nullptr, EULBFS_EINVAL, "no request in this slot");
+    if (what == EULBFS_SCALAR_DIAG && !out_on_device && out && bytes >= EULBFS_NDIAG * sizeof(double) &&
+        slot_settled(b, *sl)) {  // summed by the finishing tick: no wait
+        diag_from_sums(sl->s, b->h_sums + (size_t)slot * NRED, (double*)out);
+        return EULBFS_OK;
+    }
     const int rc = eulbfs_query(sl->s, what, out, bytes, out_on_device);
     if (rc != EULBFS_OK) b->err = sl->s->err;
     return rc;
@@ -1091,8 +1201,10 @@ int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot)
 {
     Slot* sl = batch_slot(b, slot);
     if (!sl) return set_err(b ? &b->err : nullptr, EULBFS_EINVAL, "no request in this slot");
-    (void)hipStreamSynchronize(b->stream);  // its planes may still be in use by enqueued launches
-    eulbfs_destroy(sl->s);
+    // an unfinished request's planes may still be in use by enqueued launches
+    const bool settled = slot_settled(b, *sl);
+    if (!settled) (void)hipStreamSynchronize(b->stream);
+    free_solver(sl->s, false);
     arena_free(b, sl->off, sl->bytes);
     *sl = Slot();
     return EULBFS_OK;
@@ -1102,9 +1214,14 @@ int eulbfs_batch_destroy(eulbfs_batch_t b)
 {
     if (!b) return EULBFS_OK;
     (void)hipStreamSynchronize(b->stream);
+    if (b->upload) (void)hipStreamSynchronize(b->upload);
     for (auto& sl : b->slots)
-        if (sl.s) eulbfs_destroy(sl.s);
+        if (sl.s) free_solver(sl.s, false);
     for (auto& te : b->events) (void)hipEventDestroy(te.ev);
+    if (b->h_sums) (void)hipHostFree(b->h_sums);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->stage_done) (void)hipEventDestroy(b->stage_done);
+    if (b->upload) (void)hipStreamDestroy(b->upload);
     for (int k = 0; k < 2; ++k) {
         if (b->h_desc[k]) (void)hipHostFree(b->h_desc[k]);
         if (b->h_tiles[k]) (void)hipHostFree(b->h_tiles[k]);
