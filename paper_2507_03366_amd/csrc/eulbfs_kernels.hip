@@ -238,13 +238,23 @@ __global__ void __launch_bounds__(TX* TY)
 
 // One stage of every grid of a batch.  tile_req maps a tile of the
 // concatenated tile list to its request; workgroups loop over the tiles
-// (persistent grid), so one launch covers grids of any size mix.
+// (persistent grid), so one launch covers grids of any size mix.  Every tile
+// is visited once: XCD x covers [x per_xcd, (x + 1) per_xcd) with its nb >= 1
+// workgroups.
 template <typename R, int LAT, int FAST, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_batched(const BatchDesc<R>* __restrict__ descs, const int* __restrict__ tile_req, int ntiles,
                     StageCoef K, int stage)
 {
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // XCD x (workgroups x, x + 8, ...) walks the x-th contiguous eighth of the
+    // tile list, so neighbouring tiles of a request share one L2
+    // (a grid smaller than NXCD walks the list plainly)
+    const bool split = (int)gridDim.x >= NXCD;
+    const int x = split ? blockIdx.x % NXCD : 0, r = split ? blockIdx.x / NXCD : blockIdx.x;
+    const int nb = split ? ((int)gridDim.x - x + NXCD - 1) / NXCD : (int)gridDim.x;  // workgroups on this XCD
+    const int per_xcd = split ? (ntiles + NXCD - 1) / NXCD : ntiles;
+    const int t_end = min(ntiles, (x + 1) * per_xcd);
+    for (int t = x * per_xcd + r; t < t_end; t += nb) {
         const BatchDesc<R>& D = descs[tile_req[t]];
         const int lt = t - D.tile0;  // tile index within its request, 0 <= lt < tiles of the request
         const State<R>& in = D.W[stage];
