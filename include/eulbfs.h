@@ -223,7 +223,7 @@ const char* eulbfs_last_error(eulbfs_t h);
 
 /* ---------------------------------------------------------------------------
  * Batched solves (many independent grids of uneven size advanced by one
- * persistent launch per RK stage).  A batch owns one device arena; requests
+ * launch per RK stage over the tiles of all of them).  A batch owns one device arena; requests
  * are admitted into slots while their footprint fits the HBM budget.
  * ------------------------------------------------------------------------- */
 typedef struct eulbfs_batch* eulbfs_batch_t;
@@ -238,8 +238,10 @@ int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision,
 /* Footprint in the arena of one request with these parameters. */
 size_t eulbfs_batch_request_bytes(const eulbfs_params* prm);
 
-/* Admit a request that will run nsteps steps: copies its initial state into
- * the arena (synchronises the stream).  EULBFS_EBUSY when no slot or not
+/* Admit a request that will run nsteps steps.  Its initial state is copied
+ * into the arena before the call returns (host planes through pinned memory
+ * on the batch's own upload stream, which the batch stream waits for) without
+ * waiting for the ticks in flight.  EULBFS_EBUSY when no slot or not
  * enough contiguous arena is free; EULBFS_EINVAL for bad parameters or a
  * precision that differs from the batch's.  *slot receives the slot index.
  * The request steps with the batched kernel (tile 32 x 8) whatever its
@@ -249,19 +251,24 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
 
 /* Advance every resident unfinished request by the same number of steps:
  * min(steps, the smallest number of steps any of them still has to run),
- * with one persistent launch per RK stage (per h/g lattice present) over the
- * tiles of all of them.  Asynchronous: enqueues and returns. */
+ * with one launch per RK stage (per h/g lattice and fast-path group present)
+ * over the tiles of all of them.  Enqueues and returns; waits only while two
+ * earlier ticks are still running on the device.  A tick that finishes a
+ * request also enqueues its FP64 integrals, copied to pinned host memory. */
 int eulbfs_batch_tick(eulbfs_batch_t b, int32_t steps);
 
 /* Slots whose requests have finished on the device (up to cap), in slot
  * order.  Does not block. */
 int eulbfs_batch_poll(eulbfs_batch_t b, int32_t* done, int32_t cap, int32_t* n);
 
-/* eulbfs_query on the request in a slot (synchronises). */
+/* eulbfs_query on the request in a slot.  EULBFS_SCALAR_DIAG of a finished
+ * request (as reported by eulbfs_batch_poll) into host memory is read from the
+ * pinned copy without waiting; every other query synchronises. */
 int eulbfs_batch_query(eulbfs_batch_t b, int32_t slot, int32_t what, void* out, size_t bytes,
                        int32_t out_on_device);
 
-/* Free a slot and its arena range (synchronises). */
+/* Free a slot and its arena range.  Waits for the stream only when the request
+ * has not finished on the device (its planes may still be in use). */
 int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot);
 
 int eulbfs_batch_destroy(eulbfs_batch_t b);

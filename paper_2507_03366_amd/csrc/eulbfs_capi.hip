@@ -780,8 +780,8 @@ const char* eulbfs_last_error(eulbfs_t h)
 // A batch owns one arena of device memory.  Each admitted request becomes a
 // solver whose workspace is a range of the arena, so initialisation, queries
 // and checkpoints are the single-solver code.  A tick advances every resident
-// unfinished request by the same number of steps with one persistent launch
-// per RK stage over the concatenated tile lists of all of them.
+// unfinished request by the same number of steps with one launch per RK stage
+// over the concatenated tile lists of all of them.
 // ===========================================================================
 namespace {
 
@@ -820,7 +820,6 @@ struct eulbfs_batch {
     int* h_tiles[2] = {nullptr, nullptr};
     hipEvent_t upload_done[2] = {nullptr, nullptr};
     int parity = 0;
-    int grid_blocks = 0;
     int64_t tick = 0;
     std::vector<TickEvent> events;  // recent ticks
     int64_t completed_tick = 0;     // every tick < completed_tick has completed
@@ -966,7 +965,7 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
             for (int g = 0; g < NGROUP; ++g)
                 if (ntiles[g])
                     HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g], g >= 4 ? 5 : 9, g & 3,
-                                                    K[stage], stage, b->grid_blocks, b->stream));
+                                                    K[stage], stage, b->stream));
     // requests finished by this tick: their FP64 sums go to pinned memory
     for (int k : act) {
         Slot& sl = b->slots[k];
@@ -1095,16 +1094,10 @@ int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision,
                    hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->upload, hipStreamNonBlocking) == hipSuccess;  // default priority
     ok = ok && hipEventCreateWithFlags(&b->stage_done, hipEventDisableTiming) == hipSuccess;
-    int dev = 0, cus = 0;
-    ok &= hipGetDevice(&dev) == hipSuccess;
-    ok &= hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
     if (!ok) {
         eulbfs_batch_destroy(b);
-        return set_err(err, EULBFS_EDEVICE, "batch set-up failed (pinned tables, events or device query)");
+        return set_err(err, EULBFS_EDEVICE, "batch set-up failed (pinned tables, streams or events)");
     }
-    // the persistent grid: every resident workgroup of the batched kernel
-    const int per_cu = precision == EULBFS_FP32 ? batched_blocks_per_cu<float>() : batched_blocks_per_cu<double>();
-    b->grid_blocks = cus * std::max(per_cu, 1);
     *out = b;
     return EULBFS_OK;
 }

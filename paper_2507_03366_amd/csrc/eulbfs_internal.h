@@ -61,9 +61,7 @@ hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, 
                          hipStream_t st);
 template <typename R>
 hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
-                                const StageCoef& K, int stage, int grid, hipStream_t st);
-template <typename R>
-int batched_blocks_per_cu();
+                                const StageCoef& K, int stage, hipStream_t st);
 template <typename R>
 hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,
                          hipStream_t st);

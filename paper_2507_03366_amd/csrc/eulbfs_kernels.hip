@@ -236,32 +236,27 @@ __global__ void __launch_bounds__(TX* TY)
     stage_tile<R, LAT, FAST, TX, TY>(P, K, in, Wn, out, fsdot, (t % tiles_x) * TX, (t / tiles_x) * TY);
 }
 
-// One stage of every grid of a batch.  tile_req maps a tile of the
-// concatenated tile list to its request; workgroups loop over the tiles
-// (persistent grid), so one launch covers grids of any size mix.  Every tile
-// is visited once: XCD x covers [x per_xcd, (x + 1) per_xcd) with its nb >= 1
-// workgroups.
+// One stage of every grid of a batch: one workgroup per tile of the
+// concatenated tile list of all resident requests (tile_req maps a tile to
+// its request), so one launch covers grids of any size mix.  Consecutive
+// tiles go to one XCD, as in k_stage_fused.  (A persistent grid looping over
+// the tiles held more registers per thread, one wave fewer per SIMD in FP32,
+// and ran 20-30 % slower.)
 template <typename R, int LAT, int FAST, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_batched(const BatchDesc<R>* __restrict__ descs, const int* __restrict__ tile_req, int ntiles,
                     StageCoef K, int stage)
 {
-    // XCD x (workgroups x, x + 8, ...) walks the x-th contiguous eighth of the
-    // tile list, so neighbouring tiles of a request share one L2
-    // (a grid smaller than NXCD walks the list plainly)
-    const bool split = (int)gridDim.x >= NXCD;
-    const int x = split ? blockIdx.x % NXCD : 0, r = split ? blockIdx.x / NXCD : blockIdx.x;
-    const int nb = split ? ((int)gridDim.x - x + NXCD - 1) / NXCD : (int)gridDim.x;  // workgroups on this XCD
-    const int per_xcd = split ? (ntiles + NXCD - 1) / NXCD : ntiles;
-    const int t_end = min(ntiles, (x + 1) * per_xcd);
-    for (int t = x * per_xcd + r; t < t_end; t += nb) {
-        const BatchDesc<R>& D = descs[tile_req[t]];
-        const int lt = t - D.tile0;  // tile index within its request, 0 <= lt < tiles of the request
-        const State<R>& in = D.W[stage];
-        const State<R>& out = D.W[stage == 2 ? 0 : stage + 1];
-        stage_tile<R, LAT, FAST, TX, TY>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX,
-                                         (lt / D.tiles_x) * TY);
-    }
+    const int per_xcd = (ntiles + NXCD - 1) / NXCD;
+    const int b = blockIdx.x;
+    const int t = (b % NXCD) * per_xcd + b / NXCD;
+    if (t >= ntiles) return;
+    const BatchDesc<R>& D = descs[tile_req[t]];
+    const int lt = t - D.tile0;  // tile index within its request, 0 <= lt < tiles of the request
+    const State<R>& in = D.W[stage];
+    const State<R>& out = D.W[stage == 2 ? 0 : stage + 1];
+    stage_tile<R, LAT, FAST, TX, TY>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX,
+                                     (lt / D.tiles_x) * TY);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,28 +619,28 @@ hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, 
 
 template <typename R, int LAT, int FAST>
 static void launch_batched_t(const BatchDesc<R>* descs, const int* tile_req, int ntiles, const StageCoef& K,
-                             int stage, int g, hipStream_t st)
+                             int stage, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, BATCH_TX, BATCH_TY>), dim3(g), dim3(BATCH_TX * BATCH_TY), 0,
-                       st, descs, tile_req, ntiles, K, stage);
+    const int per_xcd = (ntiles + NXCD - 1) / NXCD;
+    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, BATCH_TX, BATCH_TY>), dim3(per_xcd * NXCD),
+                       dim3(BATCH_TX * BATCH_TY), 0, st, descs, tile_req, ntiles, K, stage);
 }
 
 // Requests of one batched launch share the lattice and the fast-path flags.
 template <typename R>
 hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
-                                const StageCoef& K, int stage, int grid, hipStream_t st)
+                                const StageCoef& K, int stage, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    const int g = std::min(grid, ntiles);
     const int f = fast & (FAST_HALF | FAST_UCP);
 #define EULBFS_BATCHED(LATV)                                                                                    \
     switch (f) {                                                                                                \
-        case FAST_HALF: launch_batched_t<R, LATV, FAST_HALF>(descs, tile_req, ntiles, K, stage, g, st); break;   \
-        case FAST_UCP: launch_batched_t<R, LATV, FAST_UCP>(descs, tile_req, ntiles, K, stage, g, st); break;     \
+        case FAST_HALF: launch_batched_t<R, LATV, FAST_HALF>(descs, tile_req, ntiles, K, stage, st); break;      \
+        case FAST_UCP: launch_batched_t<R, LATV, FAST_UCP>(descs, tile_req, ntiles, K, stage, st); break;        \
         case FAST_HALF | FAST_UCP:                                                                              \
-            launch_batched_t<R, LATV, FAST_HALF | FAST_UCP>(descs, tile_req, ntiles, K, stage, g, st);           \
+            launch_batched_t<R, LATV, FAST_HALF | FAST_UCP>(descs, tile_req, ntiles, K, stage, st);              \
             break;                                                                                              \
-        default: launch_batched_t<R, LATV, 0>(descs, tile_req, ntiles, K, stage, g, st); break;                  \
+        default: launch_batched_t<R, LATV, 0>(descs, tile_req, ntiles, K, stage, st); break;                     \
     }
     if (lattice == 5) {
         EULBFS_BATCHED(5)
@@ -654,26 +649,6 @@ hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, 
     }
 #undef EULBFS_BATCHED
     return hipGetLastError();
-}
-
-// Resident workgroups per CU of the batched stage kernel (the smallest over
-// its lattice and fast-path instantiations).
-template <typename R>
-int batched_blocks_per_cu()
-{
-    using Kernel = void (*)(const BatchDesc<R>*, const int*, int, StageCoef, int);
-    constexpr int TX = BATCH_TX, TY = BATCH_TY;
-    const Kernel ks[] = {k_stage_batched<R, 9, 0, TX, TY>, k_stage_batched<R, 9, 1, TX, TY>,
-                         k_stage_batched<R, 9, 2, TX, TY>, k_stage_batched<R, 9, 3, TX, TY>,
-                         k_stage_batched<R, 5, 0, TX, TY>, k_stage_batched<R, 5, 1, TX, TY>,
-                         k_stage_batched<R, 5, 2, TX, TY>, k_stage_batched<R, 5, 3, TX, TY>};
-    int n = 1 << 30;
-    for (Kernel k : ks) {
-        int m = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k, TX * TY, 0) != hipSuccess) return 0;
-        n = std::min(n, m);
-    }
-    return n;
 }
 
 template <typename R>
@@ -749,8 +724,7 @@ hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial,
     template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
     template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);   \
     template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, const StageCoef&,  \
-                                                int, int, hipStream_t);                                            \
-    template int batched_blocks_per_cu<R>();
+                                                int, hipStream_t);
 
 EULBFS_INSTANTIATE(double)
 EULBFS_INSTANTIATE(float)

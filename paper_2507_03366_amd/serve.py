@@ -6,7 +6,7 @@ of them droplets impacting the cold wall at a drawn Weber and Reynolds
 number).  The server keeps every admitted request resident in one device
 arena (eulbfs_batch_*), admits waiting requests first-come first-served as
 slots and arena bytes free up, advances all resident requests together by
-one persistent launch per RK stage per tick, and retires each request as soon
+one launch per RK stage per tick, and retires each request as soon
 as its fixed step budget is done.  It reports solves per second and the
 p50/p99 time from arrival to result.
 
