@@ -44,7 +44,7 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #              write 1 GiB)
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_kernels.hip and build.py).
-COUNTS_FINGERPRINT = "353a549ef39a8bef"
+COUNTS_FINGERPRINT = "cb2e082df5fed780"
 COUNTS = {
     "fp64/32x8": {"f64": 1238.1, "valu": 1232.9, "hbm": 31856469},
     "fp64/64x4": {"f64": 1363.6, "valu": 1382.1, "hbm": 31861973},
