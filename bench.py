@@ -203,6 +203,15 @@ def main():
     s.close()
     if diag["nonfinite"] != 0:
         raise SystemExit("state became non-finite during the benchmark")
+    # the same steps with the host hand-over included: create from host planes
+    # (upload), step, read the conserved state back (download); not `value`
+    t0 = time.perf_counter()
+    s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_SPLIT if sched[0] == E.KERNEL_SPLIT else E.KERNEL_FUSED,
+                 tile=(sched[1], sched[2]), stream=stream)
+    s.step(args.steps)
+    s.conserved()
+    pcie_s = time.perf_counter() - t0
+    s.close()
 
     cells = pr.cells
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
@@ -256,6 +265,8 @@ def main():
                      "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                              "alg_bytes_per_launch": int(alg_bytes_per_launch), "bytes_per_cell_step": bpcs}},
+        "host_handover": {"mlups": round(pr.cells * args.steps / pcie_s / 1e6, 2), "seconds": round(pcie_s, 4),
+                          "what": "create from host planes + the timed steps + W read back to the host"},
         "diagnostics_after": {k: float(v) for k, v in diag.items()},
     }
     if args.serving:
