@@ -205,6 +205,31 @@ def three_phase_stefan(nx: int = 256, ny: int = 8, H0: float = 128.0, ratio: flo
     return pr, st
 
 
+def stefan_full_freezing(ratio: float, nx: int = 32, ny: int = 1, H0: float = 12.0, ste: float = 0.25,
+                         T0: float = 0.1, T_w: float = -2.0, latent: float = 250.0, rho_g: float = 0.01,
+                         **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.2 with its printed temperatures and latent heat (T_0 = 0.1, T_w = -2,
+    L = 250, T_m = 0, C_p,s = C_p,l, lambda_s = lambda_l), C_p taken from the Stefan
+    number Ste = C_p (T_m - T_w) / L, run until the whole liquid column is frozen.
+    The conductivity 0.4 C_p keeps the liquid diffusivity at 0.4 whatever Ste is
+    (the paper prints only the ratio).  The paper gives no gas data; the gas is
+    1/100 of the liquid density here (at 1/1000 the contracting cases,
+    rho_s/rho_l >= 1.15, go unstable once the freezing front enters the gas side
+    of the diffuse interface) with the liquid's thermal diffusivity and ten times
+    its kinematic viscosity."""
+    cp = ste * latent / (0.0 - T_w)
+    pr = Problem(
+        nx=nx, ny=ny, rho=(ratio, 1.0, rho_g), mu=(0.01, 0.01, 0.1 * rho_g),
+        lam=(0.4 * cp, 0.4 * cp, 0.4 * cp * rho_g), cp=(cp, cp, cp), latent=latent,
+        sigma=0.01, periodic_y=True,
+        walls={"x-": Wall(NOSLIP, DIRICHLET, T_w), "x+": Wall(NOSLIP, ADIABATIC)},
+    ).replace(**kw)
+    X, _ = cell_centres(pr)
+    st = uniform_state(pr, T0=T0)
+    st.C = layer_profile(X, H0, pr.xi)
+    return pr, st
+
+
 def film_freezing(n: int = 256, height: float = 0.3, ratio: float = 0.917, ste: float = 0.05,
                   bond: float = 1.0, seed: int = 0, amp: float = 1e-3, **kw) -> Tuple[Problem, InitialState]:
     """Sec. 3.3: film of height 0.3 n on a cold bottom wall in a closed box."""

@@ -31,6 +31,64 @@ def neumann_front(ste: float, alpha_s: float, t: float) -> float:
     return 2.0 * neumann_k(ste) * math.sqrt(alpha_s * t)
 
 
+def neumann_two_phase_k(st_s: float, st_l: float, alpha_s: float, alpha_l: float) -> float:
+    """Two-phase Neumann constant (Sec. 3.1, liquid above the melting point):
+
+        St_s / (e^{k^2} erf k) - St_l sqrt(a_l/a_s) / (e^{k^2 a_s/a_l} erfc(k sqrt(a_s/a_l))) = k sqrt(pi)
+
+    with St_s = C_p,s (T_m - T_b)/L and St_l = C_p,l (T_0 - T_m)/L.  This is the
+    textbook balance of latent heat against the conductive fluxes of the two
+    erf/erfc profiles; Eq. (60) prints erf where the liquid term needs erfc (the
+    liquid profile decays to T_0 far from the front), and its form with erf has no
+    root for the Sec. 3.1 parameters.  The left side falls monotonically in k
+    from +inf, so bisection on (0, 3) finds the one root."""
+    r = math.sqrt(alpha_s / alpha_l)
+
+    def lhs(k):
+        return (st_s / (math.exp(k * k) * math.erf(k))
+                - st_l / r / (math.exp(k * k * r * r) * math.erfc(k * r)) - k * math.sqrt(math.pi))
+
+    lo, hi = 1e-12, 3.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if lhs(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def neumann_two_phase_T(x: np.ndarray, t: float, k: float, T_b: float, T_m: float, T_0: float,
+                        alpha_s: float, alpha_l: float) -> np.ndarray:
+    """Temperature of the two-phase Neumann solution (Eq. 59 with the liquid
+    branch written with erfc, which makes T = T_m at the front and T -> T_0 far
+    from it; the printed liquid branch is neither).  Front at X_i = 2 k sqrt(a_s t)."""
+    from scipy.special import erf, erfc
+
+    xi = 2.0 * k * math.sqrt(alpha_s * t)
+    sol = T_b + (T_m - T_b) * erf(x / (2.0 * np.sqrt(alpha_s * t))) / math.erf(k)
+    kl = k * math.sqrt(alpha_s / alpha_l)
+    liq = T_0 - (T_0 - T_m) * erfc(x / (2.0 * np.sqrt(alpha_l * t))) / math.erfc(kl)
+    return np.where(x < xi, sol, liq)
+
+
+def stefan_full_freezing_height(H0: float, ratio: float, xi: float) -> float:
+    """Final solid height of the three-phase Stefan problem (Sec. 3.2) on a diffuse
+    interface.
+
+    Sharp interface: a frozen column of height H_f held the liquid column H_0 =
+    (rho_s/rho_l) H_f, so H_f = H_0 rho_l / rho_s.  In the model the volume source
+    of the phase field (Eq. 40) is C (1 - rho_s/rho_l) dF_s/dt.  Where the order
+    parameter is below 1 a cell that freezes completely gains F_s = C, so it
+    contributes C^2 (1 - r) instead of C (1 - r) to the condensed volume (r =
+    rho_s/rho_l).  Summed over the column the deficit is (1 - r) D with D the
+    integral of C (1 - C) across the interface, xi/4 for the tanh profile of Eq.
+    (61).  Mass balance H_f = H_0 + (1 - r)(H_f - D) then gives
+    H_f = (H_0 - (1 - r) xi/4) / r, which tends to H_0 / r as xi / H_0 -> 0.
+    """
+    return (H0 - (1.0 - ratio) * xi / 4.0) / ratio
+
+
 def stefan_three_phase_interface(H0: float, ratio: float, ste: float, alpha_s: float, t: float) -> float:
     """Liquid-gas interface of the three-phase Stefan problem (Sec. 3.2): the
     frozen layer of thickness s was liquid of thickness s rho_s/rho_l, so the

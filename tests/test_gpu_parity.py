@@ -300,3 +300,33 @@ def test_conductive_freezing_neumann_on_gpu():
         s.close()
     x_front = d["solid"] / (pr.ny * pr.dx)
     assert abs(x_front - A.neumann_front(0.1, 0.4, 20000 * pr.dt)) < 0.5
+
+
+@pytest.mark.parametrize("ratio", [0.8, 1.2])
+def test_full_freezing_height_on_gpu(oracle, ratio):
+    """Sec. 3.2 run to full freezing (12 000 steps) on the GPU, expanding and
+    contracting: the same state as the oracle to 1e-10 and the final solid height
+    of the diffuse-interface closed form (H_0 - (1 - r) xi/4) / r within 0.05 cell."""
+    import analytic as A
+
+    H0 = 12.0
+    pr, st = PB.stefan_full_freezing(ratio, H0=H0, ny=4)  # the library needs ny >= 4
+    w6, _, d = _parity_run(oracle, pr, st, 12000)
+    H_f = d["solid"] / (pr.ny * pr.dx)
+    assert abs(H_f - A.stefan_full_freezing_height(H0, ratio, pr.xi)) < 0.05
+
+
+def test_two_phase_neumann_on_gpu(oracle):
+    """Sec. 3.1 with its printed parameters (liquid at T_0 = 1, L = 250) for 8000
+    steps on the GPU: the oracle's state to 1e-10 and the front within 0.1 cell of
+    the two-phase Neumann front (Eq. 60 with erfc)."""
+    import analytic as A
+
+    pr, st = PB.conductive_freezing(nx=128, ny=4, ste=1.0 / 250.0)
+    walls = dict(pr.walls)
+    walls["x+"] = PB.Wall(PB.NOSLIP, PB.DIRICHLET, 1.0)
+    pr = pr.replace(walls=walls)
+    st.T[:] = 1.0
+    _, _, d = _parity_run(oracle, pr, st, 8000)
+    k = A.neumann_two_phase_k(1.0 / 250.0, 1.0 / 250.0, 0.4, 0.4)
+    assert abs(d["solid"] / pr.ny - 2.0 * k * (0.4 * 8000 * pr.dt) ** 0.5) < 0.1

@@ -3,11 +3,12 @@
 Each test checks the oracle against something other than itself: a moment
 identity printed in the paper (Eq. 11) or implied by the equilibria, a closed
 form (Neumann front, Laplace law, shear-wave decay, three-phase Stefan
-interface), a textbook scheme the method reduces to exactly, an invariant
+interface and full-freezing height), a textbook scheme the method reduces to exactly, an invariant
 (conservation, symmetry), or a special case of the closure.  The comments
 name the mistake each one is there to catch.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -276,6 +277,85 @@ def test_three_phase_stefan_interface(oracle):
     prim = oracle.primitives(pr, W)
     frozen = prim[2][0] > 0.999
     assert np.abs(prim[4][0][frozen]).max() < 1e-12
+
+
+def _golden(name):
+    """key = values lines of a fixture under tests/golden (numbers only)."""
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                key, vals = line.split("=")
+                out[key.strip()] = [float(x) for x in vals.split()]
+    return out
+
+
+SEC32 = _golden("three_phase_stefan_sec32.txt")
+SEC31 = _golden("conductive_freezing_sec31.txt")
+
+
+def test_conductive_freezing_two_phase_neumann(oracle):
+    """Sec. 3.1 with its printed parameters (liquid at T_0 = 1 above T_m = 0, cold
+    wall T_b = -1, right wall held at T_0, L = 250, alpha = 0.4): after 8000 steps
+    the temperature away from the front cell is within 0.01 of the two-phase
+    Neumann profile (Eq. 59, liquid branch with erfc) and the front
+    (sum of F_s) within 0.1 cell of 2 k sqrt(alpha_s t), k from Eq. (60) with erfc.
+    The liquid superheat lowers k by 2.6 %, which the front resolves, and the
+    liquid's erfc profile is absent from the one-phase problem.  Catches a wrong
+    heat flux in the liquid or across the front, a wrong Dirichlet ghost and a
+    latent heat taken in the wrong place."""
+    g = {k: v[0] for k, v in SEC31.items()}
+    oracle.set_threads(1)
+    nx, steps = 128, 8000
+    lam = g["alpha_s"] * g["rho_s"] * g["cp_s"]
+    pr, st = PB.conductive_freezing(nx=nx, ny=1, ste=1.0 / g["L"])
+    walls = dict(pr.walls)
+    walls["x-"] = PB.Wall(PB.NOSLIP, PB.DIRICHLET, g["T_b"])
+    walls["x+"] = PB.Wall(PB.NOSLIP, PB.DIRICHLET, g["T_0"])
+    pr = pr.replace(walls=walls, rho=(g["rho_s"], g["rho_l"], 1.0), cp=(g["cp_s"], g["cp_l"], 1.0),
+                    lam=(lam, lam, lam), latent=g["L"], T_s=g["T_m"], T_l=g["T_m"])
+    st.T[:] = g["T_0"]
+    W, _ = oracle.run(pr, st, steps)
+    t = steps * pr.dt
+    st_s = g["cp_s"] * (g["T_m"] - g["T_b"]) / g["L"]
+    st_l = g["cp_l"] * (g["T_0"] - g["T_m"]) / g["L"]
+    k = A.neumann_two_phase_k(st_s, st_l, g["alpha_s"], g["alpha_l"])
+    x_i = 2.0 * k * math.sqrt(g["alpha_s"] * t)
+    front = oracle.diagnostics(pr, W)[3] / (pr.ny * pr.dx)
+    assert abs(front - x_i) < 0.1
+    assert abs(front - A.neumann_front(st_s, g["alpha_s"], t)) > 0.1  # the superheat matters
+    X, _ = PB.cell_centres(pr)
+    T = oracle.primitives(pr, W)[0][0]
+    Tex = A.neumann_two_phase_T(X[0], t, k, g["T_b"], g["T_m"], g["T_0"], g["alpha_s"], g["alpha_l"])
+    # left half: the right wall at T_0 stands in for an unbounded liquid
+    away = (np.abs(X[0] - x_i) > 1.5) & (X[0] < nx / 2)
+    assert np.abs(T - Tex)[away].max() < 0.01
+
+
+@pytest.mark.parametrize("ratio", SEC32["rho_s_over_rho_l"])
+def test_three_phase_stefan_full_freezing_height(oracle, ratio):
+    """Sec. 3.2 (Fig. 6): once the whole column has frozen, the solid height is
+    H_0 rho_l/rho_s, shifted by the diffuse-interface term (1 - r) xi/4 of the
+    C-weighted volume source of Eq. (40) (closed form in analytic.py).  Run with
+    the printed T_0, T_w, L and the largest printed Ste for every printed density
+    ratio.  Catches a wrong sign or a dropped factor C or (1 - rho_s/rho_l) in the
+    volume sources of Eqs. (26) and (40), a solid fraction that counts gas, and
+    a lost or doubled lagged dF_s/dt."""
+    oracle.set_threads(1)
+    H0, xi = 12.0, SEC32["xi"][0]
+    pr, st = PB.stefan_full_freezing(ratio, H0=H0, ste=max(SEC32["ste"]), T0=SEC32["T_0"][0],
+                                     T_w=SEC32["T_w"][0], latent=SEC32["L"][0])
+    assert pr.xi == xi and pr.cp[0] == pr.cp[1] and pr.lam[0] == pr.lam[1]
+    W, fs = oracle.run(pr, st, 12000)
+    d = oracle.diagnostics(pr, W)
+    H_f = d[3] / (pr.ny * pr.dx)
+    assert abs(H_f - A.stefan_full_freezing_height(H0, ratio, xi)) < 0.05
+    assert abs(H_f - H0 / ratio) < 0.3  # the paper's sharp-interface relation
+    prim = oracle.primitives(pr, W)
+    condensed = W[4] > 0.5
+    assert prim[1][condensed].max() == 0.0  # every condensed cell is frozen
+    assert np.abs(prim[4]).max() < 1e-4
 
 
 def test_shear_wave_decay(oracle):
