@@ -125,7 +125,7 @@ typedef struct {
     double gx, gy;        /* gravity; G = rho g in Eq. (51)              */
     eulbfs_bc bc[4];
     int32_t tile_x, tile_y; /* fused-kernel tile (32x8, 64x4, 16x16, 64x8,
-                               32x16); 0 picks 32x8; AUTO ignores it     */
+                               32x16, 32x32); 0 picks 32x8; AUTO ignores it */
     int32_t reserved[6];
 } eulbfs_params;
 

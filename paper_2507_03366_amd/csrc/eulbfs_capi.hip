@@ -78,10 +78,10 @@ std::string check(const eulbfs_params* p)
         if (b.heat < 0 || b.heat > 1) return "unknown heat boundary rule";
         if (!(b.theta_deg > 0 && b.theta_deg < 180)) return "contact angle must be in (0, 180) deg";
     }
-    const int tiles[][2] = {{0, 0}, {32, 8}, {64, 4}, {16, 16}, {64, 8}, {32, 16}};
+    const int tiles[][2] = {{0, 0}, {32, 8}, {64, 4}, {16, 16}, {64, 8}, {32, 16}, {32, 32}};
     bool ok = false;
     for (auto& t : tiles) ok |= (p->tile_x == t[0] && p->tile_y == t[1]);
-    if (!ok) return "tile must be 0x0, 32x8, 64x4, 16x16, 64x8 or 32x16";
+    if (!ok) return "tile must be 0x0, 32x8, 64x4, 16x16, 64x8, 32x16 or 32x32";
     return "";
 }
 
@@ -91,6 +91,7 @@ int tile_of(const eulbfs_params* p)
     if (p->tile_x == 16 && p->tile_y == 16) return TILE_16x16;
     if (p->tile_x == 64 && p->tile_y == 8) return TILE_64x8;
     if (p->tile_x == 32 && p->tile_y == 16) return TILE_32x16;
+    if (p->tile_x == 32 && p->tile_y == 32) return TILE_32x32;
     return TILE_32x8;
 }
 
@@ -758,7 +759,7 @@ int eulbfs_destroy(eulbfs_t h)
 int eulbfs_schedule(eulbfs_t h, int32_t* kernel, int32_t* tile_x, int32_t* tile_y)
 {
     if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
-    static const int TX[NTILES] = {32, 64, 16, 64, 32}, TY[NTILES] = {8, 4, 16, 8, 16};
+    static const int TX[NTILES] = {32, 64, 16, 64, 32, 32}, TY[NTILES] = {8, 4, 16, 8, 16, 32};
     const bool split = h->sched == EULBFS_KERNEL_SPLIT;
     if (kernel) *kernel = h->sched;
     if (tile_x) *tile_x = split ? 0 : TX[h->tile];

@@ -26,7 +26,7 @@ struct SplitScratch {
     size_t fstride;  // elements between flux planes
 };
 
-enum { TILE_32x8 = 0, TILE_64x4 = 1, TILE_16x16 = 2, TILE_64x8 = 3, TILE_32x16 = 4, NTILES = 5 };
+enum { TILE_32x8 = 0, TILE_64x4 = 1, TILE_16x16 = 2, TILE_64x8 = 3, TILE_32x16 = 4, TILE_32x32 = 5, NTILES = 6 };
 
 constexpr int NXCD = 8;  // accelerator complex dies of an MI355X, each with its own L2
 

@@ -22,13 +22,15 @@
 namespace eulbfs {
 
 // ---------------------------------------------------------------------------
-// Per-cell update shared by the fused and the split stage kernels.
+// Per-cell update shared by the fused and the split stage kernels: Wk is the
+// cell's stage input, Wnk its W^n (the same values in the first stage), fsd
+// its lagged dF_s/dt.
 // ---------------------------------------------------------------------------
 template <typename R, int FAST = 0>
 __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef& K, const R c[NPRIM + 1],
-                                            const Cons<R>& Wk, R dudx, R dvdy, R drhodx, R drhody, R dmudx,
-                                            R dmudy, const R dF[5], const State<R>& Wn, const State<R>& out,
-                                            R* fsdot, R* resid, size_t resid_stride, size_t q)
+                                            const Cons<R>& Wk, const Cons<R>& Wnk, R fsd, R dudx, R dvdy,
+                                            R drhodx, R drhody, R dmudx, R dmudy, const R dF[5],
+                                            const State<R>& out, R* fsdot, R* resid, size_t resid_stride, size_t q)
 {
     R Fl = R(0);
     if (P.surf_model == 1) {
@@ -36,7 +38,6 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
         closure<FAST>(P, Wk.H, clamp01(Wk.C), fl, T);
         Fl = R(fl);
     }
-    const R fsd = fsdot[q];
     R S[5];
     sources<R, FAST>(P, c, Fl, fsd, dudx, dvdy, drhodx, drhody, dmudx, dmudy, S);
     R res[5];
@@ -47,8 +48,7 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
         for (int k = 0; k < 5; ++k) resid[k * resid_stride + q] = res[k];
         return;
     }
-    Cons<R> wn = Wk;
-    if (K.ca != 0.0) wn = read_at(Wn, q);
+    const Cons<R>& wn = Wnk;
     const double cdt = K.cc * P.dt;
     const double Hnew = K.ca * wn.H + K.cb * Wk.H + cdt * (double)res[0];
     const R ca = R(K.ca), cb = R(K.cb), cdtr = R(cdt);
@@ -73,8 +73,13 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
 //
 // LDS: the W tile with three halo layers is only needed until the primitive
 // fields exist, so the face fluxes reuse its bytes; the primitive planes
-// (tile + two halo layers) live through the whole stage.
+// (tile + two halo layers) live through the whole stage.  The density plane
+// is stored when it fits in the 160 KB of a CU; otherwise (32 x 32 in FP64)
+// rho is recomputed from C and F_s where it is read, by the same expression
+// as in primitives(), so both forms give the same bits.
 // ---------------------------------------------------------------------------
+constexpr size_t LDS_PER_CU = 160 * 1024;
+
 template <typename R, int TX, int TY>
 struct FusedLds {
     static constexpr int W3 = TX + 2 * NG, H3 = TY + 2 * NG;
@@ -83,7 +88,17 @@ struct FusedLds {
     static constexpr size_t BYTES_W = (size_t)W3 * H3 * (2 * sizeof(double) + 3 * sizeof(R));
     static constexpr size_t BYTES_F = (size_t)5 * (NFX + NFY) * sizeof(R);
     static constexpr size_t BYTES_U = BYTES_W > BYTES_F ? BYTES_W : BYTES_F;
+    static constexpr bool RHO = BYTES_U + (size_t)(NPRIM + 1) * W2 * H2 * sizeof(R) <= LDS_PER_CU;
+    static constexpr int NPL = RHO ? NPRIM + 1 : NPRIM;  // stored primitive planes
 };
+
+// Density of a primitive-plane entry (Eq. 7 with the clamped C and F_s).
+template <typename R, bool RHO, int N>
+__device__ __forceinline__ R plane_rho(const DevParams& P, const R (*sP)[N], int q)
+{
+    if constexpr (RHO) return sP[NPRIM][q];
+    else return mix<R>(P.rho, clamp01(sP[VC][q]), sP[VFS][q]);
+}
 
 // One tile of one stage: cells [i0, i0+TX) x [j0, j0+TY) of the grid described
 // by P.  Every thread of the workgroup must call it (it synchronises).
@@ -95,7 +110,8 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     constexpr int NT = TX * TY;
     constexpr int W3 = L::W3, H3 = L::H3, W2 = L::W2, H2 = L::H2, NFX = L::NFX, NFY = L::NFY;
     __shared__ __align__(16) char sU[L::BYTES_U];
-    __shared__ R sP[NPRIM + 1][W2 * H2];
+    constexpr bool RHO = L::RHO;
+    __shared__ R sP[L::NPL][W2 * H2];
     double* sH = reinterpret_cast<double*>(sU);                                // H, then C
     double* sC = sH + W3 * H3;
     R* sW = reinterpret_cast<R*>(sU + (size_t)2 * W3 * H3 * sizeof(double));  // p, Mx, My
@@ -113,16 +129,27 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
         sW[2 * W3 * H3 + q] = w.my;
         sC[q] = w.C;
     };
+    // every load of a thread is issued before the first LDS store, so the
+    // memory latency is paid once rather than once per pass
+    constexpr int NQ = W3 * H3, NIT = (NQ + NT - 1) / NT;
+    Cons<R> w[NIT];
     if (i0 >= NG && j0 >= NG && i0 + TX + NG <= P.nx && j0 + TY + NG <= P.ny) {
-        for (int q = tid; q < W3 * H3; q += NT) {
-            const int li = q % W3, lj = q / W3;
-            stage(q, read_cell(in, P.pitch, i0 + li - NG, j0 + lj - NG));
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * NT;
+            if (q < NQ) w[it] = read_cell(in, P.pitch, i0 + q % W3 - NG, j0 + q / W3 - NG);
         }
     } else {
-        for (int q = tid; q < W3 * H3; q += NT) {
-            const int li = q % W3, lj = q / W3;
-            stage(q, load_bc(P, in, i0 + li - NG, j0 + lj - NG));
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * NT;
+            if (q < NQ) w[it] = load_bc(P, in, i0 + q % W3 - NG, j0 + q / W3 - NG);
         }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * NT;
+        if (q < NQ) stage(q, w[it]);
     }
     __syncthreads();
 
@@ -140,15 +167,21 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
         primitives<R, FAST>(P, w, pr);
         pr[VMU] = R(chem_potential(P, w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3], sC[q3 - W3]));
 #pragma unroll
-        for (int k = 0; k <= NPRIM; ++k) sP[k][q] = pr[k];
+        for (int k = 0; k < L::NPL; ++k) sP[k][q] = pr[k];
     }
     __syncthreads();
 
-    // 3. every face of the tile once (fluxes overwrite the dead W tile)
+    // 3. every face of the tile once (fluxes overwrite the dead W tile).  The
+    // x faces are padded to whole waves in the iteration space, so every wave
+    // takes either the x or the y branch in a pass, never both.
     const R i2dx = R(P.inv_2dx);
     const R c_sh = R(0.5 * P.dx - P.delta_t) * i2dx, c_h = R(0.5 * P.dx) * i2dx, c_ds = R(P.delta_t) * i2dx;
     constexpr int NF = NFX + NFY;
-    for (int f = tid; f < NF; f += NT) {
+    constexpr int NFXP = (NFX + 63) / 64 * 64;
+    static_assert(NT % 64 == 0, "whole waves per workgroup");
+    for (int fp = tid; fp < NFXP + NFY; fp += NT) {
+        if (fp >= NFX && fp < NFXP) continue;  // padding of the x faces
+        const int f = fp < NFXP ? fp : fp - NFXP + NFX;  // storage index: x faces, then y faces
         Bases<R> X;
         R F[5];
         if (f < NFX) {
@@ -158,8 +191,8 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             for (int k = 0; k < NPRIM; ++k)
                 face_bases<R, FAST>(sP[k], a, 1, W2, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
                                     X.dm[k]);
-            X.rho_a = sP[NPRIM][a];
-            X.rho_b = sP[NPRIM][a + 1];
+            X.rho_a = plane_rho<R, RHO>(P, sP, a);
+            X.rho_b = plane_rho<R, RHO>(P, sP, a + 1);
             face_flux<R, LAT, FAST>(P, X, F);
             const int gi = i0 + fi;
             if (!P.periodic_x) {
@@ -178,8 +211,8 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
                 face_bases<R, FAST>(sP[ks], a, W2, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
                                     X.dm[k]);
             }
-            X.rho_a = sP[NPRIM][a];
-            X.rho_b = sP[NPRIM][a + W2];
+            X.rho_a = plane_rho<R, RHO>(P, sP, a);
+            X.rho_b = plane_rho<R, RHO>(P, sP, a + W2);
             face_flux<R, LAT, FAST>(P, X, F);
             const int gj = j0 + fj;
             if (!P.periodic_y) {
@@ -193,12 +226,22 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             sF[4 * NF + f] = F[4];
         }
     }
-    __syncthreads();
-
-    // 4. cell update
+    // 4. cell update.  The cell's stage input, W^n and dF_s/dt are loaded
+    // before the barrier: a wave that is done with its faces waits for them
+    // while the last faces are computed.
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
-    if (i < 0 || j < 0 || i >= P.nx || j >= P.ny) return;  // no barrier follows in this tile
+    const bool own = i < P.nx && j < P.ny;
+    const size_t q = (size_t)j * P.pitch + i;
+    Cons<R> wk{}, wnk{};
+    R fsd = R(0);
+    if (own) {
+        wk = read_cell(in, P.pitch, i, j);
+        wnk = read_at(Wn, q);
+        fsd = fsdot[q];
+    }
+    __syncthreads();
+    if (!own) return;  // no barrier follows in this tile
     const int fl = ty * (TX + 1) + tx;
     const int fb = NFX + ty * TX + tx;
     const R idx = R(1.0 / P.dx);
@@ -209,16 +252,15 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     const int c2 = (ty + 2) * W2 + tx + 2;
     R c[NPRIM + 1];
 #pragma unroll
-    for (int k = 0; k <= NPRIM; ++k) c[k] = sP[k][c2];
+    for (int k = 0; k < NPRIM; ++k) c[k] = sP[k][c2];
+    c[NPRIM] = plane_rho<R, RHO>(P, sP, c2);
     const R dudx = (sP[VU][c2 + 1] - sP[VU][c2 - 1]) * i2dx;
     const R dvdy = (sP[VV][c2 + W2] - sP[VV][c2 - W2]) * i2dx;
-    const R drx = (sP[NPRIM][c2 + 1] - sP[NPRIM][c2 - 1]) * i2dx;
-    const R dry = (sP[NPRIM][c2 + W2] - sP[NPRIM][c2 - W2]) * i2dx;
+    const R drx = (plane_rho<R, RHO>(P, sP, c2 + 1) - plane_rho<R, RHO>(P, sP, c2 - 1)) * i2dx;
+    const R dry = (plane_rho<R, RHO>(P, sP, c2 + W2) - plane_rho<R, RHO>(P, sP, c2 - W2)) * i2dx;
     const R dmx = (sP[VMU][c2 + 1] - sP[VMU][c2 - 1]) * i2dx;
     const R dmy = (sP[VMU][c2 + W2] - sP[VMU][c2 - W2]) * i2dx;
-    const size_t q = (size_t)j * P.pitch + i;
-    const Cons<R> wk = read_cell(in, P.pitch, i, j);
-    cell_update<R, FAST>(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, (R*)nullptr, 0, q);
+    cell_update<R, FAST>(P, K, c, wk, wnk, fsd, dudx, dvdy, drx, dry, dmx, dmy, dF, out, fsdot, (R*)nullptr, 0, q);
 }
 
 // One stage of one grid.  Workgroups are dispatched round-robin over the
@@ -377,7 +419,8 @@ __global__ void k_split_update(DevParams P, StageCoef K, const R* prim, size_t p
     const R dmy = (pm[c2 + gpitch] - pm[c2 - gpitch]) * i2dx;
     const size_t q = (size_t)j * P.pitch + i;
     const Cons<R> wk = read_cell(in, P.pitch, i, j);
-    cell_update(P, K, c, wk, dudx, dvdy, drx, dry, dmx, dmy, dF, Wn, out, fsdot, resid, resid_stride, q);
+    const Cons<R> wnk = read_at(Wn, q);
+    cell_update(P, K, c, wk, wnk, fsdot[q], dudx, dvdy, drx, dry, dmx, dmy, dF, out, fsdot, resid, resid_stride, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,6 +635,7 @@ static hipError_t launch_fused_f(const DevParams& P, int tile, const StageCoef& 
         case TILE_64x8: return launch_fused_t<R, LAT, FAST, 64, 8>(P, K, in, Wn, out, fsdot, st);
         case TILE_64x4: return launch_fused_t<R, LAT, FAST, 64, 4>(P, K, in, Wn, out, fsdot, st);
         case TILE_32x16: return launch_fused_t<R, LAT, FAST, 32, 16>(P, K, in, Wn, out, fsdot, st);
+        case TILE_32x32: return launch_fused_t<R, LAT, FAST, 32, 32>(P, K, in, Wn, out, fsdot, st);
         default: return launch_fused_t<R, LAT, FAST, 32, 8>(P, K, in, Wn, out, fsdot, st);
     }
 }

@@ -11,7 +11,7 @@ from paper_2507_03366_amd import problems as PB
 
 pytestmark = pytest.mark.gpu
 
-TILES = ((32, 8), (64, 4), (16, 16), (64, 8), (32, 16))
+TILES = ((32, 8), (64, 4), (16, 16), (64, 8), (32, 16), (32, 32))
 
 
 def _ragged(lattice_hg=9, periodic_x=False):

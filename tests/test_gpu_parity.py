@@ -191,7 +191,7 @@ def test_impact_reduced_1000_steps(oracle):
     _parity_run(oracle, pr, st, 1000)
 
 
-@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (16, 16), (64, 8), (32, 16)])
+@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (16, 16), (64, 8), (32, 16), (32, 32)])
 def test_tiles_agree_on_ragged_grid(oracle, tile):
     pr, st = PB.static_droplet(n=64, R=16)
     pr = pr.replace(nx=70, ny=45, sigma=0.015625)
