@@ -275,6 +275,55 @@ def static_droplet(n: int = 512, R: float = 128.0, theta_deg: float = 90.0, rati
     return pr, st
 
 
+# Table 3 of the paper (SI units): liquid and solid properties of the two fluids
+# of Sec. 3.4, the wall temperature and the melting point.
+TABLE3 = {
+    "water": {"rho": (917.0, 999.0), "cp": (2100.0, 4220.0), "lam": (2.16, 0.581), "latent": 333400.0,
+              "T_m": 0.0, "T_w": -10.0},
+    "hexadecane": {"rho": (833.0, 774.0), "cp": (1800.0, 2310.0), "lam": (0.15, 0.15), "latent": 230000.0,
+                   "T_m": 18.0, "T_w": 15.0},
+}
+
+
+def table3_droplet(fluid: str, theta_deg: float, ratio: float = None, nx: int = 400, ny: int = 200,
+                   R: float = 50.0, alpha_l: float = 0.05, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.4 volume-change runs (Figs. 11-12): a sessile droplet of one of the
+    Table 3 fluids on a cold wall at contact angle theta, on the paper's 400 x 200
+    grid.  Lattice map: the liquid is rho_l = 1, C_p,l = 1, alpha_l = alpha_l; the
+    solid keeps the Table 3 ratios rho_s/rho_l (or `ratio`), C_p,s/C_p,l and
+    lambda_s/lambda_l; T_m - T_w maps to 1 and L to L / (C_p,l (T_m - T_w)).  The
+    droplet starts at T_m (the pre-nucleation state).  The paper gives no gas data
+    and no lattice viscosity or surface tension: the gas follows the other
+    configurations (1/1000 of the liquid density, the liquid's diffusivity and
+    kinematic viscosity); mu_l = 0.05 and sigma from Ca = 0.01 on the thermal
+    velocity alpha_l / R, as for the 512 x 512 droplet (with mu_l = alpha_l / 8 the
+    light gas at a 135 deg contact line goes unstable within 300 steps)."""
+    m = TABLE3[fluid]
+    rs, rl = m["rho"]
+    r = rs / rl if ratio is None else ratio
+    cps, cpl = m["cp"]
+    lams, laml = m["lam"]
+    cp_s = cps / cpl
+    lam_l = alpha_l * 1.0 * 1.0
+    lam_s = lam_l * lams / laml
+    latent = m["latent"] / (cpl * (m["T_m"] - m["T_w"]))
+    mu_l = 0.05
+    rho_g = RHO_G
+    sigma = mu_l * (alpha_l / R) / 0.01
+    pr = Problem(
+        nx=nx, ny=ny, rho=(r, 1.0, rho_g), mu=(mu_l, mu_l, _gas_mu(mu_l, rho_g)),
+        lam=(lam_s, lam_l, _gas_lambda(lam_l, rho_g)), cp=(cp_s, 1.0, 1.0), latent=latent,
+        sigma=sigma,
+        walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0, theta_deg), "y+": Wall()},
+    ).replace(**kw)
+    X, Y = cell_centres(pr)
+    st = uniform_state(pr)
+    th = math.radians(theta_deg)
+    Rc = R * math.sqrt((math.pi / 2.0) / (th - math.sin(th) * math.cos(th)))
+    st.C = droplet_profile(X, Y, 0.5 * pr.nx * pr.dx, -Rc * math.cos(th), Rc, pr.xi)
+    return pr, st
+
+
 def impact_droplet(n: int = 256, we: float = 50.0, re: float = 500.0, U: float = 0.05,
                    ratio: float = 0.917, ste: float = 0.1, supercool: float = 0.5,
                    theta_deg: float = 90.0, **kw) -> Tuple[Problem, InitialState]:
