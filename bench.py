@@ -43,8 +43,9 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #              per dispatch; the factors make a 1 GiB device copy read and
 #              write 1 GiB)
 # valid only for the sources and compile flags with this fingerprint (sha256
-# of csrc/eulbfs_device.h, csrc/eulbfs_kernels.hip and build.py).
-COUNTS_FINGERPRINT = "12459e1127a1d635"
+# of csrc/eulbfs_device.h, csrc/eulbfs_internal.h, csrc/eulbfs_kernels.hip and
+# build.py).
+COUNTS_FINGERPRINT = "9e49f23b2cb3b62c"
 COUNTS = {
     "fp64/32x8": {"f64": 1238.1, "valu": 1235.6, "hbm": 31963437},
     "fp64/64x4": {"f64": 1260.1, "valu": 1292.8, "hbm": 31949797},
@@ -91,7 +92,8 @@ def kernel_fingerprint() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("csrc/eulbfs_device.h", "csrc/eulbfs_kernels.hip", "build.py"):  # sources and compile flags
+    for f in ("csrc/eulbfs_device.h", "csrc/eulbfs_internal.h", "csrc/eulbfs_kernels.hip",
+              "build.py"):  # sources and compile flags
         with open(os.path.join(ROOT, "paper_2507_03366_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -30,9 +30,13 @@ enum { TILE_32x8 = 0, TILE_64x4 = 1, TILE_16x16 = 2, TILE_64x8 = 3, TILE_32x16 =
 
 constexpr int NXCD = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
+// Tile of the batched stage kernel: for the serving mix (grids of 64^2 to 512^2
+// in FP32 mode) 32 x 16 beat 32 x 8, 64 x 8 and 32 x 32 (67, 60, 66 and 48
+// solves/s).
+constexpr int BATCH_TX = 32, BATCH_TY = 16;
+
 // One request of a batch: its constants, its three copies of W (W^n, W1, W2)
 // and its dF_s/dt plane, and where its tiles start in the batch's tile list.
-constexpr int BATCH_TX = 32, BATCH_TY = 8;
 template <typename R>
 struct BatchDesc {
     DevParams P;
