@@ -358,6 +358,30 @@ def test_three_phase_stefan_full_freezing_height(oracle, ratio):
     assert np.abs(prim[4]).max() < 1e-4
 
 
+def test_sources_of_a_uniform_freezing_state(oracle):
+    """Eqs. (26), (27), (40) and (51) on a uniform, partly frozen, moving state with
+    a given dF_s/dt: every face flux cancels against its neighbour, so the residual
+    is the source vector alone: rho c_s^2 (1 - rho_s/rho_l) dF_s/dt for p,
+    -c_s^2 rho u dF_s/dt (F_IBM of Eq. 27) for the momenta, C (1 - rho_s/rho_l)
+    dF_s/dt for C and C_p T div u = 0 for H.  Catches a flipped or dropped F_IBM
+    in both momentum rows at once (invisible to the equivariance checks) and the
+    sign or weighting of the volume sources."""
+    pr = PB.Problem(nx=4, ny=4, rho=(0.8, 1.0, 0.1), mu=(0.05, 0.05, 0.01), lam=(0.4, 0.4, 0.04),
+                    latent=2.0, sigma=0.01, periodic_x=True, periodic_y=True)
+    C, Fl, u, v, fsd = 0.7, 0.4, 0.013, -0.021, 0.0123
+    st = PB.uniform_state(pr, T0=0.0, Fl0=Fl, C0=C)
+    st.u[:] = u
+    st.v[:] = v
+    W = oracle.init(pr, st)
+    R, _, _ = oracle.residual(pr, W, np.full((pr.ny, pr.nx), fsd))
+    Fs = C * (1.0 - Fl)  # solid fraction of the condensed phase (gas never solid)
+    rho = Fs * 0.8 + (1.0 - Fs) * C * 1.0 + (1.0 - Fs) * (1.0 - C) * 0.1  # Eq. (7)
+    ex = 1.0 - 0.8 / 1.0
+    expect = [0.0, rho * CS2 * ex * fsd, -CS2 * rho * u * fsd, -CS2 * rho * v * fsd, C * ex * fsd]
+    for k in range(5):
+        np.testing.assert_allclose(R[k], expect[k], rtol=1e-12, atol=1e-16)
+
+
 def test_shear_wave_decay(oracle):
     """u_x = U sin(k y) decays as exp(-nu k^2 t): pins tau_f and the sign of the
     non-equilibrium part of f* (the printed '-' makes the wave grow)."""
