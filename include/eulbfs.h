@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define EULBFS_ABI_VERSION 1u
+#define EULBFS_ABI_VERSION 2u
 
 /* status codes */
 #define EULBFS_OK 0
@@ -84,7 +84,19 @@ typedef struct {
     int32_t reserved;
     double T_w;       /* EULBFS_HEAT_DIRICHLET wall temperature           */
     double theta_deg; /* equilibrium contact angle through the liquid, deg */
+    double theta_adv; /* contact-angle hysteresis window [theta_rec,      */
+    double theta_rec; /* theta_adv], deg; 0, 0: none (see below)          */
 } eulbfs_bc;
+/* Wetting wall (Secs. 3.4-3.5): the ghost C of layer k (k = 1, 2, 3 outward)
+ * is C of the mirrored cell + (2k - 1) dx (4/xi) cos(theta) C_w (1 - C_w), C_w
+ * the first interior cell, i.e. dC/dn = -(4/xi) cos(theta) C (1 - C) at the
+ * wall; theta = 90 deg is a plain no-flux wall.  Sec. 3.5 names advancing and
+ * receding angles without a rule for them; with a window, theta is the
+ * apparent angle of the first three interior cells along the normal (dC/dn at
+ * the wall from the quadratic through their centres) clamped to [theta_rec,
+ * theta_adv]: a contact line inside the window keeps its angle, one outside
+ * is driven to the nearer bound.  Where C_w (1 - C_w) <= 1e-3 theta_deg is
+ * used.  A window needs 0 < theta_rec <= theta_deg <= theta_adv < 180. */
 
 /* Problem parameters (all in lattice units).
  * Readings of the paper implemented by this library:

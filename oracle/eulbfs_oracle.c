@@ -75,6 +75,14 @@
  *   R14 Initial state from (T, F_l, C, u, v, p): H = (1-F_l)(H_s + C_p^S (T -
  *       T_s)) + F_l (H_l + C_p^L (T - T_l)), M = rho c_s^2 (u, v) with rho from
  *       the closure of that H.
+ *   R23 Contact-angle hysteresis (Sec. 3.5 gives advancing and receding angles
+ *       but no rule): a wall with a window [theta_rec, theta_adv] reads the
+ *       apparent angle of the first two interior cells along the normal,
+ *       cos(theta_app) = -(C_2 - C_w) / (dx (4/xi) C_w (1 - C_w)), and uses
+ *       theta_app clamped to the window in place of theta in the wetting rule
+ *       of R13 (a contact line inside the window keeps its angle, one outside
+ *       is driven to the nearer bound).  Where C_w (1 - C_w) <= 1e-3 (no
+ *       interface at the wall) theta is used.
  */
 #include "eulbfs_oracle.h"
 
@@ -273,9 +281,10 @@ static void load_interior(grid_t* g, const double* W)
 }
 
 /* Wall rule of R13 applied to one ghost cell.  side: 0 x-, 1 x+, 2 y-, 3 y+.
- * m: the mirrored cell, w: the first interior cell, layer k = 1..3. */
-static void wall_ghost(const or_params* P, int side, const cell_t* m, const cell_t* w, int k,
-                       double Wg[5])
+ * m: the mirrored cell, w and w2: the first and second interior cells along
+ * the wall normal, layer k = 1..3. */
+static void wall_ghost(const or_params* P, int side, const cell_t* m, const cell_t* w, const cell_t* w2,
+                       const cell_t* w3, int k, double Wg[5])
 {
     const or_bc* b = &P->bc[side];
     int normal = side < 2 ? 2 : 3;  /* index of the normal momentum */
@@ -294,7 +303,14 @@ static void wall_ghost(const or_params* P, int side, const cell_t* m, const cell
     /* wetting: dC/dn_in = -(4/xi) cos(theta) C (1 - C) */
     double Cw = w->W[4];
     double d = (2 * k - 1) * P->dx;
-    Wg[4] = m->W[4] + d * (4.0 / P->xi) * cos(b->theta_deg * M_PI / 180.0) * Cw * (1.0 - Cw);
+    double cth = cos(b->theta_deg * M_PI / 180.0);
+    if (b->theta_adv > 0.0 && Cw * (1.0 - Cw) > 1e-3) { /* R23 */
+        double dn = -2.0 * Cw + 3.0 * w2->W[4] - w3->W[4]; /* dC/dn_in at the wall, times dx */
+        double c_app = -dn / (P->dx * (4.0 / P->xi) * Cw * (1.0 - Cw));
+        double c_adv = cos(b->theta_adv * M_PI / 180.0), c_rec = cos(b->theta_rec * M_PI / 180.0);
+        cth = c_app < c_adv ? c_adv : (c_app > c_rec ? c_rec : c_app);
+    }
+    Wg[4] = m->W[4] + d * (4.0 / P->xi) * cth * Cw * (1.0 - Cw);
     if (b->heat == OR_HEAT_DIRICHLET) {
         double Fl, Tm;
         or_closure(P, m->W[0], m->W[4], &Fl, &Tm);
@@ -318,8 +334,8 @@ static void fill_ghosts(grid_t* g)
                 memcpy(gl->W, at(g, wrap(-k, nx), j)->W, sizeof gl->W);
                 memcpy(gr->W, at(g, wrap(nx - 1 + k, nx), j)->W, sizeof gr->W);
             } else {
-                wall_ghost(P, 0, at(g, k - 1, j), at(g, 0, j), k, gl->W);
-                wall_ghost(P, 1, at(g, nx - k, j), at(g, nx - 1, j), k, gr->W);
+                wall_ghost(P, 0, at(g, k - 1, j), at(g, 0, j), at(g, 1, j), at(g, 2, j), k, gl->W);
+                wall_ghost(P, 1, at(g, nx - k, j), at(g, nx - 1, j), at(g, nx - 2, j), at(g, nx - 3, j), k, gr->W);
             }
         }
     }
@@ -332,8 +348,8 @@ static void fill_ghosts(grid_t* g)
                 memcpy(gb->W, at(g, i, wrap(-k, ny))->W, sizeof gb->W);
                 memcpy(gt->W, at(g, i, wrap(ny - 1 + k, ny))->W, sizeof gt->W);
             } else {
-                wall_ghost(P, 2, at(g, i, k - 1), at(g, i, 0), k, gb->W);
-                wall_ghost(P, 3, at(g, i, ny - k), at(g, i, ny - 1), k, gt->W);
+                wall_ghost(P, 2, at(g, i, k - 1), at(g, i, 0), at(g, i, 1), at(g, i, 2), k, gb->W);
+                wall_ghost(P, 3, at(g, i, ny - k), at(g, i, ny - 1), at(g, i, ny - 2), at(g, i, ny - 3), k, gt->W);
             }
         }
     }
@@ -580,6 +596,13 @@ static int check(const or_params* P)
     if (P->bc[0].periodic != P->bc[1].periodic || P->bc[2].periodic != P->bc[3].periodic) return OR_EINVAL;
     if (!P->bc[0].periodic && P->nx < NG) return OR_EINVAL;
     if (!P->bc[2].periodic && P->ny < NG) return OR_EINVAL;
+    for (int s = 0; s < 4; ++s) {
+        const or_bc* b = &P->bc[s];
+        if (b->theta_adv == 0.0 && b->theta_rec == 0.0) continue;
+        if (!(b->theta_rec > 0.0 && b->theta_rec <= b->theta_deg && b->theta_deg <= b->theta_adv &&
+              b->theta_adv < 180.0))
+            return OR_EINVAL;
+    }
     return OR_OK;
 }
 

@@ -24,6 +24,7 @@ typedef struct {
     int32_t pad;
     double T_w;       /* wall temperature for OR_HEAT_DIRICHLET */
     double theta_deg; /* contact angle; 90 = plain no-flux wall */
+    double theta_adv, theta_rec; /* hysteresis window (R23); 0, 0: none */
 } or_bc;
 
 typedef struct {

@@ -29,7 +29,8 @@ def build(force: bool = True) -> str:
 
 class _BC(ct.Structure):
     _fields_ = [("periodic", ct.c_int32), ("flow", ct.c_int32), ("heat", ct.c_int32),
-                ("pad", ct.c_int32), ("T_w", ct.c_double), ("theta_deg", ct.c_double)]
+                ("pad", ct.c_int32), ("T_w", ct.c_double), ("theta_deg", ct.c_double),
+                ("theta_adv", ct.c_double), ("theta_rec", ct.c_double)]
 
 
 class _Params(ct.Structure):
@@ -92,6 +93,7 @@ def params(pr) -> _Params:
             P.bc[k].periodic = 0
             P.bc[k].flow, P.bc[k].heat = w.flow, w.heat
             P.bc[k].T_w, P.bc[k].theta_deg = w.T_w, w.theta_deg
+            P.bc[k].theta_adv, P.bc[k].theta_rec = w.theta_adv, w.theta_rec
     return P
 
 

@@ -77,6 +77,10 @@ std::string check(const eulbfs_params* p)
         if (b.flow < 0 || b.flow > 2) return "unknown flow boundary rule";
         if (b.heat < 0 || b.heat > 1) return "unknown heat boundary rule";
         if (!(b.theta_deg > 0 && b.theta_deg < 180)) return "contact angle must be in (0, 180) deg";
+        if (b.theta_adv != 0.0 || b.theta_rec != 0.0) {
+            if (!(b.theta_rec > 0 && b.theta_rec <= b.theta_deg && b.theta_deg <= b.theta_adv && b.theta_adv < 180))
+                return "hysteresis window needs 0 < theta_rec <= theta_deg <= theta_adv < 180 deg";
+        }
     }
     const int tiles[][2] = {{0, 0}, {32, 8}, {64, 4}, {16, 16}, {64, 8}, {32, 16}, {32, 32}};
     bool ok = false;
@@ -111,7 +115,11 @@ DevParams make_dev(const eulbfs_params* p)
         d.heat[s] = p->bc[s].heat;
         d.T_w[s] = p->bc[s].T_w;
         d.wet[s] = p->dx * (4.0 / p->xi) * std::cos(p->bc[s].theta_deg * M_PI / 180.0);
+        d.hyst[s] = (!p->bc[s].periodic && p->bc[s].theta_adv != 0.0) ? 1 : 0;
+        d.cos_adv[s] = std::cos(p->bc[s].theta_adv * M_PI / 180.0);
+        d.cos_rec[s] = std::cos(p->bc[s].theta_rec * M_PI / 180.0);
     }
+    d.wet_k = p->dx * (4.0 / p->xi);
     d.dx = p->dx;
     d.inv_2dx = 1.0 / (2.0 * p->dx);
     d.inv_dx2 = 1.0 / (p->dx * p->dx);

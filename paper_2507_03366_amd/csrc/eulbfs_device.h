@@ -44,6 +44,9 @@ struct DevParams {
     double expansion;    // 1 - rho_s/rho_l
     double T_w[4];
     double wet[4];       // dx (4/xi) cos(theta): ghost C offset per mirror distance
+    double wet_k;        // dx (4/xi)
+    int hyst[4];         // contact-angle hysteresis window on this wall
+    double cos_adv[4], cos_rec[4];  // cos of the advancing and receding angles
     double inv_dt;
     int fast;            // FAST_* fast paths valid for these constants
     // FAST_UCP closure constants: H_s = C_p T_s, H_l = C_p T_l + L, 1/C_p,
@@ -202,10 +205,27 @@ __device__ __forceinline__ Cons<R> read_cell(const State<R>& S, int pitch, int i
     return w;
 }
 
+// Wetting factor dx (4/xi) cos(theta) of a wall.  With a hysteresis window the
+// angle is the apparent one of the first three interior cells along the
+// inward normal (C1, C2, C3), cos = -dC/dn / ((4/xi) C1 (1 - C1)) with dC/dn at
+// the wall from the quadratic through the three cell centres, clamped to the
+// window; where C1 (1 - C1) <= 1e-3 there is no interface and the equilibrium
+// angle is used.
+__device__ __forceinline__ double wet_factor(const DevParams& P, int side, double C1, double C2, double C3)
+{
+    const double s = C1 * (1.0 - C1);
+    if (!P.hyst[side] || !(s > 1e-3)) return P.wet[side];
+    const double dn = -2.0 * C1 + 3.0 * C2 - C3;
+    const double c = fmin(fmax(-dn / (P.wet_k * s), P.cos_adv[side]), P.cos_rec[side]);
+    return P.wet_k * c;
+}
+
 // Wall rule for ghost layer k (1..3) of `side` (0 x-, 1 x+, 2 y-, 3 y+):
-// m is the mirrored interior cell, Cw the C of the first interior cell.
+// m is the mirrored interior cell, Cw the C of the first interior cell, wet
+// the wall's wetting factor (wet_factor).
 template <typename R>
-__device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int k, const Cons<R>& m, double Cw)
+__device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int k, const Cons<R>& m, double Cw,
+                                              double wet)
 {
     Cons<R> g;
     g.p = m.p;
@@ -217,7 +237,7 @@ __device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int 
     const R gt = f == FLOW_NOSLIP ? -mt : mt;
     g.mx = xside ? gn : gt;
     g.my = xside ? gt : gn;
-    g.C = m.C + ((2 * k - 1) * P.wet[side]) * Cw * (1.0 - Cw);
+    g.C = m.C + ((2 * k - 1) * wet) * Cw * (1.0 - Cw);
     if (P.heat[side] == HEAT_DIRICHLET) {
         double Fl, Tm;
         closure(P, m.H, clamp01(m.C), Fl, Tm);
@@ -242,15 +262,17 @@ __device__ __forceinline__ Cons<R> load_x(const DevParams& P, const State<R>& S,
 {
     if (i >= 0 && i < P.nx) return read_cell(S, P.pitch, i, j);
     if (P.periodic_x) return read_cell(S, P.pitch, wrap(i, P.nx), j);
-    int side, k, m, first;
+    int side, k, m, first, in;
     if (i < 0) {
-        side = 0; k = -i; m = k - 1; first = 0;
+        side = 0; k = -i; m = k - 1; first = 0; in = 1;
     } else {
-        side = 1; k = i - P.nx + 1; m = P.nx - k; first = P.nx - 1;
+        side = 1; k = i - P.nx + 1; m = P.nx - k; first = P.nx - 1; in = -1;
     }
     const Cons<R> wm = read_cell(S, P.pitch, m, j);
-    const double Cw = S.C[(size_t)j * P.pitch + first];
-    return wall_ghost(P, side, k, wm, Cw);
+    const size_t o = (size_t)j * P.pitch + first;
+    const double Cw = S.C[o];
+    const double wet = P.hyst[side] ? wet_factor(P, side, Cw, S.C[o + in], S.C[o + 2 * in]) : P.wet[side];
+    return wall_ghost(P, side, k, wm, Cw, wet);
 }
 
 // Conserved state at any (i, j) of the grid extended by the three-layer
@@ -265,15 +287,18 @@ __device__ __forceinline__ Cons<R> load_bc(const DevParams& P, const State<R>& S
     j = min(max(j, -NG), P.ny + NG - 1);
     if (j >= 0 && j < P.ny) return load_x(P, S, i, j);
     if (P.periodic_y) return load_x(P, S, i, wrap(j, P.ny));
-    int side, k, m, first;
+    int side, k, m, first, in;
     if (j < 0) {
-        side = 2; k = -j; m = k - 1; first = 0;
+        side = 2; k = -j; m = k - 1; first = 0; in = 1;
     } else {
-        side = 3; k = j - P.ny + 1; m = P.ny - k; first = P.ny - 1;
+        side = 3; k = j - P.ny + 1; m = P.ny - k; first = P.ny - 1; in = -1;
     }
     const Cons<R> wm = load_x(P, S, i, m);
     const double Cw = load_x(P, S, i, first).C;
-    return wall_ghost(P, side, k, wm, Cw);
+    const double wet = P.hyst[side] ? wet_factor(P, side, Cw, load_x(P, S, i, first + in).C,
+                                                 load_x(P, S, i, first + 2 * in).C)
+                                    : P.wet[side];
+    return wall_ghost(P, side, k, wm, Cw, wet);
 }
 
 // Primitive record of one cell used by the face fluxes.

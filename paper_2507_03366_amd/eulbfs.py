@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, 
 FP64, FP32 = 0, 1
 KERNEL_FUSED, KERNEL_SPLIT, KERNEL_AUTO = 0, 1, 2
 INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
              W_GHOSTED=14)
 SCALAR_DIAG = 100
@@ -35,7 +35,8 @@ class EulbfsError(RuntimeError):
 
 class eulbfs_bc(ct.Structure):
     _fields_ = [("periodic", ct.c_int32), ("flow", ct.c_int32), ("heat", ct.c_int32), ("reserved", ct.c_int32),
-                ("T_w", ct.c_double), ("theta_deg", ct.c_double)]
+                ("T_w", ct.c_double), ("theta_deg", ct.c_double), ("theta_adv", ct.c_double),
+                ("theta_rec", ct.c_double)]
 
 
 class eulbfs_params(ct.Structure):
@@ -124,6 +125,7 @@ def params_from_problem(pr, precision: int = None, kernel: int = KERNEL_FUSED, t
             P.bc[k].periodic = 0
             P.bc[k].flow, P.bc[k].heat = w.flow, w.heat
             P.bc[k].T_w, P.bc[k].theta_deg = w.T_w, w.theta_deg
+            P.bc[k].theta_adv, P.bc[k].theta_rec = w.theta_adv, w.theta_rec
     P.tile_x, P.tile_y = tile
     return P
 

@@ -33,12 +33,15 @@ SIDES = ("x-", "x+", "y-", "y+")
 
 @dataclass
 class Wall:
-    """One non-periodic side: flow rule, heat rule, wall temperature, contact angle."""
+    """One non-periodic side: flow rule, heat rule, wall temperature, contact
+    angle and an optional hysteresis window [theta_rec, theta_adv] (0, 0: none)."""
 
     flow: int = NOSLIP
     heat: int = ADIABATIC
     T_w: float = 0.0
     theta_deg: float = 90.0
+    theta_adv: float = 0.0
+    theta_rec: float = 0.0
 
 
 @dataclass

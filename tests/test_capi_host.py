@@ -32,9 +32,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout_matches_header():
-    # 8 + 6*4 ints, 3 + 12 + 9 doubles, 4 bc of 32 bytes, 8 ints
-    assert ct.sizeof(E.eulbfs_bc) == 32
-    assert ct.sizeof(E.eulbfs_params) == 32 + 24 * 8 + 4 * 32 + 8 * 4
+    # 8 + 6*4 ints, 3 + 12 + 9 doubles, 4 bc of 48 bytes, 8 ints (the library
+    # itself rejects a struct_size other than its sizeof(eulbfs_params))
+    assert ct.sizeof(E.eulbfs_bc) == 48
+    assert ct.sizeof(E.eulbfs_params) == 32 + 24 * 8 + 4 * 48 + 8 * 4
     assert E.eulbfs_params.dx.offset == 32
 
 
@@ -74,6 +75,16 @@ def test_periodic_mismatch_rejected():
     P = _params()
     P.bc[0].periodic = 1
     assert "periodic" in E.eulbfs_check_params(P)
+
+
+def test_hysteresis_window_checked():
+    P = _params()
+    side = next(k for k in range(4) if not P.bc[k].periodic)
+    P.bc[side].theta_deg, P.bc[side].theta_adv, P.bc[side].theta_rec = 80.0, 100.0, 40.0
+    assert E.eulbfs_check_params(P) == ""
+    for adv, rec in ((100.0, 85.0), (75.0, 40.0), (180.0, 40.0), (100.0, 0.0)):
+        P.bc[side].theta_adv, P.bc[side].theta_rec = adv, rec
+        assert "hysteresis" in E.eulbfs_check_params(P), (adv, rec)
 
 
 def test_abi_guard():

@@ -77,6 +77,14 @@ def _cases():
         "x-": _walls(PB.NOSLIP, PB.DIRICHLET, 80.0), "x+": _walls(PB.NOSLIP, PB.ADIABATIC, 90.0)}, **ucp)))
     cases.append(("ucp_half_mushy", PB.Problem(nx=10, ny=11, T_s=-0.2, T_l=0.1, periodic_x=True, walls={
         "y-": _walls(PB.NOSLIP, PB.DIRICHLET, 110.0), "y+": _walls(PB.FREESLIP, PB.ADIABATIC, 90.0)}, **ucp)))
+    # contact-angle hysteresis windows on every wall (seeded C straddles the
+    # interface at the walls, so the apparent angles hit both bounds and the
+    # inside of the windows)
+    hw = {"x-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -1.0, 80.0, 100.0, 40.0),
+          "x+": PB.Wall(PB.FREESLIP, PB.ADIABATIC, 0.0, 90.0, 95.0, 85.0),
+          "y-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -0.5, 120.0, 150.0, 60.0),
+          "y+": PB.Wall(PB.OUTLET, PB.ADIABATIC, 0.0, 70.0, 70.0, 70.0)}
+    cases.append(("hysteresis", PB.Problem(nx=9, ny=10, walls=hw, **base)))
     return cases
 
 

@@ -460,6 +460,42 @@ def test_sessile_drop_contact_angle(oracle, theta):
     assert abs(_cap_angle(W[4]) - theta) < 3.0
 
 
+def _cap_run(oracle, theta0, wall, steps):
+    pr = PB.Problem(nx=64, ny=32, mu=(0.1, 0.1, 0.1), sigma=0.01,
+                    walls={"x-": PB.Wall(), "x+": PB.Wall(), "y-": wall, "y+": PB.Wall()})
+    th, R = math.radians(theta0), 12.0
+    Rc = R * math.sqrt((math.pi / 2) / (th - math.sin(th) * math.cos(th)))
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr)
+    st.C = PB.droplet_profile(X, Y, 32.0, -Rc * math.cos(th), Rc, 4.0)
+    W, _ = oracle.run(pr, st, steps)
+    return W
+
+
+def test_hysteresis_window_on_the_equilibrium_angle_is_the_plain_wall(oracle):
+    """A window collapsed onto theta reproduces the plain wetting wall bit for bit."""
+    oracle.set_threads(8)
+    plain = _cap_run(oracle, 75.0, PB.Wall(theta_deg=60.0), 200)
+    window = _cap_run(oracle, 75.0, PB.Wall(theta_deg=60.0, theta_adv=60.0, theta_rec=60.0), 200)
+    assert np.array_equal(plain, window)
+
+
+def test_hysteresis_pins_and_bounds_the_contact_angle(oracle):
+    """Contact-angle hysteresis (the reading of the advancing and receding angles
+    of Sec. 3.5): a 90 deg cap inside a [45, 110] deg window stays at 90 deg where
+    the plain 60 deg wall pulls it down by 20 deg in 3000 steps; outside a
+    [100, 130] window it recedes to the receding bound, outside a [60, 80]
+    window it advances to the advancing bound."""
+    oracle.set_threads(8)
+    assert _cap_angle(_cap_run(oracle, 90.0, PB.Wall(theta_deg=60.0), 3000)[4]) < 75.0
+    pinned = _cap_angle(_cap_run(oracle, 90.0, PB.Wall(theta_deg=60.0, theta_adv=110.0, theta_rec=45.0), 3000)[4])
+    assert abs(pinned - 90.0) < 2.5
+    rec = _cap_angle(_cap_run(oracle, 90.0, PB.Wall(theta_deg=115.0, theta_adv=130.0, theta_rec=100.0), 6000)[4])
+    assert abs(rec - 100.0) < 1.5
+    adv = _cap_angle(_cap_run(oracle, 90.0, PB.Wall(theta_deg=70.0, theta_adv=80.0, theta_rec=60.0), 6000)[4])
+    assert abs(adv - 80.0) < 1.5
+
+
 def test_flat_interface_at_rest(oracle):
     """Density ratio 1000, no gravity: a flat interface stays at rest (the
     literal '1+' in Eq. (34) adds mu/delta_t to the normal stress and drives a
