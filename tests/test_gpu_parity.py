@@ -226,6 +226,34 @@ def test_large_grid_2048(oracle):
     _parity_run(oracle, pr, st, 2, tol=1e-12, kernel=E.KERNEL_AUTO)
 
 
+def test_periodic_tiling_at_8192(oracle):
+    """A 64 x 64 periodic state tiled 128 x 128 times (8192 x 8192 = 67 M cells,
+    65 536 tiles of 32 x 32): after three autotuned steps every 64 x 64 block on
+    the GPU is the same bits as every other and matches the oracle's 64 x 64
+    run to 1e-12 (an indexing or tile-mapping error anywhere in the large grid
+    shows up as a block that differs)."""
+    base = dict(rho=(0.917, 1.0, 0.05), mu=(0.05, 0.04, 0.004), lam=(0.5, 0.4, 0.02), cp=(1.2, 1.0, 0.9),
+                latent=3.0, sigma=0.02, mobility=0.08, periodic_x=True, periodic_y=True)
+    small = PB.Problem(nx=64, ny=64, **base)
+    st = PB.seeded_fields(small, seed=5, amp=0.5)
+    oracle.set_threads(16)
+    Wref, _ = oracle.run(small, st, 3)
+    reps = 128
+    big = PB.Problem(nx=64 * reps, ny=64 * reps, **base)
+    tiled = PB.InitialState(*(np.tile(a, (reps, reps)) for a in (st.T, st.Fl, st.C, st.u, st.v, st.p)))
+    s = E.Solver(big, tiled, kernel=E.KERNEL_AUTO)
+    del tiled
+    try:
+        s.step(3)
+        w = s.conserved()[:5]
+    finally:
+        s.close()
+    blocks = w.reshape(5, reps, 64, reps, 64)
+    first = blocks[:, 0, :, 0, :]
+    assert (blocks == first[:, None, :, None, :]).all()
+    assert scaled_err(first, Wref).max() < 1e-12
+
+
 def test_film_full_size_256(oracle):
     pr, st = PB.film_freezing()
     _parity_run(oracle, pr, st, 20, tol=1e-12)
