@@ -70,6 +70,29 @@ def test_reduced_grid_matches_oracle(oracle, fluid, ratio, alpha, key, theta, i)
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("fluid", ["water", "hexadecane"])
+def test_reduced_grid_fp32_within_1e4(oracle, fluid):
+    """FP32 mode on the generic path (unequal C_p and lambda) with a 150 deg
+    wetting wall: relative L2 of every field within 1e-4 of the FP64 oracle
+    after 1000 steps on 100 x 50."""
+    f, ratio, alpha, key = next(c for c in FLUIDS if c[0] == fluid)
+    sigma = PB.table3_droplet(fluid, 150.0, ratio=ratio, alpha_l=alpha)[0].sigma
+    pr, st = PB.table3_droplet(fluid, 150.0, ratio=ratio, alpha_l=alpha, nx=100, ny=50, R=12.5, sigma=sigma)
+    oracle.set_threads(16)
+    Wref, _ = oracle.run(pr, st, 1000)
+    s = E.Solver(pr, st, precision=E.FP32, kernel=E.KERNEL_AUTO)
+    try:
+        s.run(1000)
+        w = s.conserved()
+    finally:
+        s.close()
+    for name, ks in (("H", [0]), ("p", [1]), ("M", [2, 3]), ("C", [4])):
+        err = np.linalg.norm((w[ks] - Wref[ks]).ravel()) / np.linalg.norm(Wref[ks].ravel())
+        print(f"{fluid} FP32 {name}: {err:.2e}")
+        assert err <= 1e-4, (name, err)
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("fluid,ratio,alpha,key,theta,i", CASES, ids=[f"{c[0]}-{int(c[4])}" for c in CASES])
 def test_volume_after_full_freezing(fluid, ratio, alpha, key, theta, i):
     pr, st = PB.table3_droplet(fluid, theta, ratio=ratio, alpha_l=alpha)
