@@ -139,17 +139,86 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             const int q = tid + it * NT;
             if (q < NQ) w[it] = read_cell(in, P.pitch, i0 + q % W3 - NG, j0 + q / W3 - NG);
         }
-    } else {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int q = tid + it * NT;
-            if (q < NQ) w[it] = load_bc(P, in, i0 + q % W3 - NG, j0 + q / W3 - NG);
+            if (q < NQ) stage(q, w[it]);
         }
-    }
+    } else {
+        // Tiles whose halo leaves the grid, in the order of load_bc (which the
+        // split path uses) and with its values: (a) cells of the grid and
+        // periodic images, plain loads; (b) x-wall ghosts of the rows that are
+        // not y-wall ghosts; (c) y-wall ghosts of every column.  A ghost's
+        // mirror and first interior cells lie inside the tile, so (b) and (c)
+        // read them from LDS.  Positions beyond the ghost ring are clamped onto
+        // it first, as in load_bc.
+        auto cl = [](int g, int n) { return min(max(g, -NG), n + NG - 1); };
+        bool inside[NIT];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int q = tid + it * NT;
-        if (q < NQ) stage(q, w[it]);
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * NT;
+            int gi = cl(i0 + q % W3 - NG, P.nx), gj = cl(j0 + q / W3 - NG, P.ny);
+            if (P.periodic_x) gi = wrap(gi, P.nx);
+            if (P.periodic_y) gj = wrap(gj, P.ny);
+            inside[it] = q < NQ && gi >= 0 && gi < P.nx && gj >= 0 && gj < P.ny;
+            if (inside[it]) w[it] = read_cell(in, P.pitch, gi, gj);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (inside[it]) stage(tid + it * NT, w[it]);
+        auto cons_at = [&](int q) {
+            Cons<R> c;
+            c.H = sH[q];
+            c.p = sW[q];
+            c.mx = sW[W3 * H3 + q];
+            c.my = sW[2 * W3 * H3 + q];
+            c.C = sC[q];
+            return c;
+        };
+        // one wall rule for the ghost at clamped normal index g (outside
+        // [0, n)); base: LDS index of normal index 0 on the ghost's line,
+        // stride: LDS step along the normal
+        auto ghost = [&](int side, int g, int n, int base, int stride) {
+            const bool lo = g < 0;
+            const int k = lo ? -g : g - n + 1;
+            const int m = lo ? k - 1 : n - k, first = lo ? 0 : n - 1, dir = lo ? 1 : -1;
+            const int qm = base + m * stride, qf = base + first * stride;
+            const double Cw = sC[qf];
+            const double wet = P.hyst[side] ? wet_factor(P, side, Cw, sC[qf + dir * stride], sC[qf + 2 * dir * stride])
+                                            : P.wet[side];
+            return wall_ghost(P, side, k, cons_at(qm), Cw, wet);
+        };
+        __syncthreads();
+        // One thread per ghost cell, the ghost columns (rows) of one side at a
+        // time: the side is a loop constant, so each wall's constants are
+        // scalar loads, and most tiles need a single pass of the first waves.
+        // Ghost columns of a side: LDS columns [0, NG - i0) below the wall at
+        // 0, [nx - i0 + NG, W3) beyond the wall at nx (the latter includes the
+        // columns past the ring of a partial tile).
+        if (!P.periodic_x) {
+            for (int sd = 0; sd < 2; ++sd) {
+                const int c0 = sd == 0 ? 0 : P.nx - i0 + NG;
+                const int nc = sd == 0 ? max(0, NG - i0) : max(0, W3 - c0);
+                for (int c = tid; c < nc * H3; c += NT) {
+                    const int lj = c / nc, li = c0 + c % nc;
+                    const int gi = cl(i0 + li - NG, P.nx), gj = cl(j0 + lj - NG, P.ny);
+                    if (P.periodic_y || (gj >= 0 && gj < P.ny))
+                        stage(lj * W3 + li, ghost(sd, gi, P.nx, lj * W3 + NG - i0, 1));
+                }
+            }
+            __syncthreads();
+        }
+        if (!P.periodic_y) {
+            for (int sd = 2; sd < 4; ++sd) {
+                const int r0 = sd == 2 ? 0 : P.ny - j0 + NG;
+                const int nr = sd == 2 ? max(0, NG - j0) : max(0, H3 - r0);
+                for (int c = tid; c < nr * W3; c += NT) {
+                    const int lj = r0 + c / W3, li = c % W3;
+                    const int gj = cl(j0 + lj - NG, P.ny);
+                    stage(lj * W3 + li, ghost(sd, gj, P.ny, (NG - j0) * W3 + li, W3));
+                }
+            }
+        }
     }
     __syncthreads();
 
