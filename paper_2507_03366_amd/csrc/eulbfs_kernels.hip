@@ -248,7 +248,20 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     constexpr int NF = NFX + NFY;
     constexpr int NFXP = (NFX + 63) / 64 * 64;
     static_assert(NT % 64 == 0, "whole waves per workgroup");
+    // A SIMD issues from its oldest ready wave first, so the oldest waves of a
+    // workgroup finish their faces early and the youngest run the end of the
+    // pass alone.  With one 1024-thread workgroup per CU a wave's priority
+    // drops with each face it has done, which keeps the waves of a SIMD abreast
+    // (2-5 % faster).  Where several workgroups share a CU the raised priority
+    // starves the others' loads instead (10-15 % slower), so smaller tiles
+    // keep the default.
+    constexpr bool PRIO = NT >= 1024;
+    if (PRIO) __builtin_amdgcn_s_setprio(3);
     for (int fp = tid; fp < NFXP + NFY; fp += NT) {
+        if (PRIO && fp != tid) {
+            if (fp < tid + 2 * NT) __builtin_amdgcn_s_setprio(2);
+            else __builtin_amdgcn_s_setprio(1);
+        }
         if (fp >= NFX && fp < NFXP) continue;  // padding of the x faces
         const int f = fp < NFXP ? fp : fp - NFXP + NFX;  // storage index: x faces, then y faces
         Bases<R> X;
@@ -295,6 +308,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             sF[4 * NF + f] = F[4];
         }
     }
+    if (PRIO) __builtin_amdgcn_s_setprio(0);
     // 4. cell update.  The cell's stage input, W^n and dF_s/dt are loaded
     // before the barrier: a wave that is done with its faces waits for them
     // while the last faces are computed.
