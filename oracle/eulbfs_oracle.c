@@ -50,7 +50,11 @@
  *       F_s = C and F_s = 0.  For C = 1 this is Eqs. (5)-(7) unchanged.  C is
  *       clamped to [0,1] wherever it enters the closure or a material
  *       property (F_s too).
- *   R8  Gradients: second-order central differences; lap(C): 5-point stencil.
+ *   R8  Gradients: the derivative at the cell centre of the parabola through
+ *       the cell and its two neighbours along each direction (second-order
+ *       central differences on a uniform mesh); lap(C): the sum over both
+ *       directions of that parabola's second derivative (the 5-point stencil
+ *       on a uniform mesh).
  *   R9  Points x_f - e_alpha delta_t with e_alpha . n = 0 lie on the face; they
  *       take the average of the two sides' extrapolations.
  *   R10 Reconstructed variables: T, C, F_s, u, v, p, mu_c.  rho and C_p at a
@@ -67,22 +71,34 @@
  *       no-slip: both momenta odd; free slip: normal odd, tangential even;
  *       outlet: both even.  Adiabatic: H even.  Dirichlet T_w: T_g = 2 T_w -
  *       T_mirror, H_g from the inverse closure.  Wetting (contact angle theta,
- *       90 deg = plain no-flux): C_g = C_mirror + (2k-1) dx (4/xi) cos(theta)
- *       C_w (1 - C_w), C_w the first interior cell.  Corners: x rule on the
- *       interior rows first, then the y rule on every column.  Fluxes on wall
- *       faces: F_p = 0 unless the wall is an outlet, F_C = 0 (no flux),
- *       F_H = 0 when adiabatic.
+ *       90 deg = plain no-flux): C_g = C_mirror + d_k (4/xi) cos(theta)
+ *       C_w (1 - C_w), C_w the first interior cell, d_k the distance between
+ *       the ghost and mirror centres ((2k-1) dx on a uniform mesh).  Corners:
+ *       x rule on the interior rows first, then the y rule on every column.
+ *       Fluxes on wall faces: F_p = 0 unless the wall is an outlet, F_C = 0
+ *       (no flux), F_H = 0 when adiabatic.
  *   R14 Initial state from (T, F_l, C, u, v, p): H = (1-F_l)(H_s + C_p^S (T -
  *       T_s)) + F_l (H_l + C_p^L (T - T_l)), M = rho c_s^2 (u, v) with rho from
  *       the closure of that H.
  *   R23 Contact-angle hysteresis (Sec. 3.5 gives advancing and receding angles
  *       but no rule): a wall with a window [theta_rec, theta_adv] reads the
- *       apparent angle of the first two interior cells along the normal,
- *       cos(theta_app) = -(C_2 - C_w) / (dx (4/xi) C_w (1 - C_w)), and uses
- *       theta_app clamped to the window in place of theta in the wetting rule
- *       of R13 (a contact line inside the window keeps its angle, one outside
- *       is driven to the nearer bound).  Where C_w (1 - C_w) <= 1e-3 (no
- *       interface at the wall) theta is used.
+ *       apparent angle of the first three interior cells along the normal,
+ *       cos(theta_app) = -(dC/dn at the wall) / ((4/xi) C_w (1 - C_w)), dC/dn
+ *       from the parabola through the three cell centres, and uses theta_app
+ *       clamped to the window in place of theta in the wetting rule of R13 (a
+ *       contact line inside the window keeps its angle, one outside is driven
+ *       to the nearer bound).  Where C_w (1 - C_w) <= 1e-3 (no interface at
+ *       the wall) theta is used.
+ *   R24 Stretched meshes (Eq. 52 is written for any mesh; the paper runs
+ *       uniform ones): a tensor product of column widths w_i and row heights
+ *       h_j.  V = w_i h_j, S = h_j on x faces and w_i on y faces; the face
+ *       centre lies w/2 from each neighbouring cell centre, so Eq. (54)
+ *       extrapolates by w_a/2 and w_b/2 on the two sides; one streaming step
+ *       delta_t for the whole mesh, at most half the smallest width.  Ghost
+ *       cells take the width of the cell they copy (mirror or periodic
+ *       image), so a wall lies midway between a ghost and its mirror and the
+ *       wetting offset of R13 uses the distance 2 s between them (s: wall to
+ *       mirror centre).  Uniform spacing dx is the case w_i = h_j = dx.
  */
 #include "eulbfs_oracle.h"
 
@@ -254,11 +270,33 @@ typedef struct {
     const or_params* P;
     int nx, ny, sx; /* sx = nx + 2 NG (row stride) */
     cell_t* c;
+    double* wx; /* widths of the nx + 2 NG columns, ghosts included (R24) */
+    double* wy; /* heights of the ny + 2 NG rows */
 } grid_t;
 
 static cell_t* at(grid_t* g, int i, int j) { return &g->c[(size_t)(j + NG) * g->sx + (i + NG)]; }
 
 static int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+/* width of column i (or height of row i), -NG <= i < n + NG */
+static double WX(const grid_t* g, int i) { return g->wx[i + NG]; }
+static double WY(const grid_t* g, int j) { return g->wy[j + NG]; }
+
+/* Interior widths from the user array (or dx), ghosts from the cell they copy:
+ * the periodic image, or the mirrored interior cell k-1 of ghost layer k (R24). */
+static void ghosted_widths(const double* w, double dx, int n, int periodic, double* out)
+{
+    for (int i = -NG; i < n + NG; ++i) {
+        int src;
+        if (i >= 0 && i < n)
+            src = i;
+        else if (periodic)
+            src = wrap(i, n);
+        else
+            src = i < 0 ? -i - 1 : 2 * n - 1 - i;
+        out[i + NG] = w ? w[src] : dx;
+    }
+}
 
 static int grid_alloc(grid_t* g, const or_params* P)
 {
@@ -267,10 +305,35 @@ static int grid_alloc(grid_t* g, const or_params* P)
     g->ny = P->ny;
     g->sx = P->nx + 2 * NG;
     g->c = (cell_t*)calloc((size_t)g->sx * (P->ny + 2 * NG), sizeof(cell_t));
-    return g->c ? 0 : -1;
+    g->wx = (double*)malloc((size_t)(P->nx + 2 * NG) * sizeof(double));
+    g->wy = (double*)malloc((size_t)(P->ny + 2 * NG) * sizeof(double));
+    if (!g->c || !g->wx || !g->wy) {
+        free(g->c); free(g->wx); free(g->wy);
+        return -1;
+    }
+    ghosted_widths(P->xw, P->dx, P->nx, P->bc[0].periodic, g->wx);
+    ghosted_widths(P->yw, P->dx, P->ny, P->bc[2].periodic, g->wy);
+    return 0;
 }
 
-static void grid_free(grid_t* g) { free(g->c); }
+static void grid_free(grid_t* g)
+{
+    free(g->c);
+    free(g->wx);
+    free(g->wy);
+}
+
+/* Distances from the wall of `side` to the centres of the first three
+ * interior cells along the inward normal. */
+static void wall_distances(const grid_t* g, int side, double s[3])
+{
+    double acc = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        double w = side == 0 ? WX(g, m) : side == 1 ? WX(g, g->nx - 1 - m) : side == 2 ? WY(g, m) : WY(g, g->ny - 1 - m);
+        s[m] = acc + 0.5 * w;
+        acc += w;
+    }
+}
 
 static void load_interior(grid_t* g, const double* W)
 {
@@ -281,10 +344,10 @@ static void load_interior(grid_t* g, const double* W)
 }
 
 /* Wall rule of R13 applied to one ghost cell.  side: 0 x-, 1 x+, 2 y-, 3 y+.
- * m: the mirrored cell, w and w2: the first and second interior cells along
- * the wall normal, layer k = 1..3. */
+ * m: the mirrored cell, w, w2, w3: the first three interior cells along the
+ * wall normal, whose centres lie s[0], s[1], s[2] from the wall; layer k = 1..3. */
 static void wall_ghost(const or_params* P, int side, const cell_t* m, const cell_t* w, const cell_t* w2,
-                       const cell_t* w3, int k, double Wg[5])
+                       const cell_t* w3, const double s[3], int k, double Wg[5])
 {
     const or_bc* b = &P->bc[side];
     int normal = side < 2 ? 2 : 3;  /* index of the normal momentum */
@@ -302,11 +365,16 @@ static void wall_ghost(const or_params* P, int side, const cell_t* m, const cell
     }
     /* wetting: dC/dn_in = -(4/xi) cos(theta) C (1 - C) */
     double Cw = w->W[4];
-    double d = (2 * k - 1) * P->dx;
+    double d = 2.0 * s[k - 1]; /* ghost centre to mirror centre (R24) */
     double cth = cos(b->theta_deg * M_PI / 180.0);
     if (b->theta_adv > 0.0 && Cw * (1.0 - Cw) > 1e-3) { /* R23 */
-        double dn = -2.0 * Cw + 3.0 * w2->W[4] - w3->W[4]; /* dC/dn_in at the wall, times dx */
-        double c_app = -dn / (P->dx * (4.0 / P->xi) * Cw * (1.0 - Cw));
+        /* dC/dn_in at the wall: derivative at 0 of the Lagrange parabola
+         * through (s[0], C_w), (s[1], C_2), (s[2], C_3) */
+        double l0 = -(s[1] + s[2]) / ((s[0] - s[1]) * (s[0] - s[2]));
+        double l1 = -(s[0] + s[2]) / ((s[1] - s[0]) * (s[1] - s[2]));
+        double l2 = -(s[0] + s[1]) / ((s[2] - s[0]) * (s[2] - s[1]));
+        double dn = l0 * Cw + l1 * w2->W[4] + l2 * w3->W[4];
+        double c_app = -dn / ((4.0 / P->xi) * Cw * (1.0 - Cw));
         double c_adv = cos(b->theta_adv * M_PI / 180.0), c_rec = cos(b->theta_rec * M_PI / 180.0);
         cth = c_app < c_adv ? c_adv : (c_app > c_rec ? c_rec : c_app);
     }
@@ -325,6 +393,8 @@ static void fill_ghosts(grid_t* g)
 {
     const or_params* P = g->P;
     int nx = g->nx, ny = g->ny;
+    double s[4][3];
+    for (int side = 0; side < 4; ++side) wall_distances(g, side, s[side]);
     /* x rule on the interior rows */
     for (int j = 0; j < ny; ++j) {
         for (int k = 1; k <= NG; ++k) {
@@ -334,8 +404,9 @@ static void fill_ghosts(grid_t* g)
                 memcpy(gl->W, at(g, wrap(-k, nx), j)->W, sizeof gl->W);
                 memcpy(gr->W, at(g, wrap(nx - 1 + k, nx), j)->W, sizeof gr->W);
             } else {
-                wall_ghost(P, 0, at(g, k - 1, j), at(g, 0, j), at(g, 1, j), at(g, 2, j), k, gl->W);
-                wall_ghost(P, 1, at(g, nx - k, j), at(g, nx - 1, j), at(g, nx - 2, j), at(g, nx - 3, j), k, gr->W);
+                wall_ghost(P, 0, at(g, k - 1, j), at(g, 0, j), at(g, 1, j), at(g, 2, j), s[0], k, gl->W);
+                wall_ghost(P, 1, at(g, nx - k, j), at(g, nx - 1, j), at(g, nx - 2, j), at(g, nx - 3, j), s[1], k,
+                           gr->W);
             }
         }
     }
@@ -348,12 +419,32 @@ static void fill_ghosts(grid_t* g)
                 memcpy(gb->W, at(g, i, wrap(-k, ny))->W, sizeof gb->W);
                 memcpy(gt->W, at(g, i, wrap(ny - 1 + k, ny))->W, sizeof gt->W);
             } else {
-                wall_ghost(P, 2, at(g, i, k - 1), at(g, i, 0), at(g, i, 1), at(g, i, 2), k, gb->W);
-                wall_ghost(P, 3, at(g, i, ny - k), at(g, i, ny - 1), at(g, i, ny - 2), at(g, i, ny - 3), k, gt->W);
+                wall_ghost(P, 2, at(g, i, k - 1), at(g, i, 0), at(g, i, 1), at(g, i, 2), s[2], k, gb->W);
+                wall_ghost(P, 3, at(g, i, ny - k), at(g, i, ny - 1), at(g, i, ny - 2), at(g, i, ny - 3), s[3], k,
+                           gt->W);
             }
         }
     }
 }
+
+/* R8: first and second derivative at the middle point of the parabola through
+ * (-hm, vm), (0, v0), (hp, vp); on a uniform mesh (hm = hp = dx) these are
+ * (vp - vm) / (2 dx) and (vp - 2 v0 + vm) / dx^2. */
+static double d1(double hm, double hp, double vm, double v0, double vp)
+{
+    return (hm * hm * (vp - v0) + hp * hp * (v0 - vm)) / (hm * hp * (hm + hp));
+}
+
+static double d2(double hm, double hp, double vm, double v0, double vp)
+{
+    return 2.0 * ((vp - v0) / hp - (v0 - vm) / hm) / (hm + hp);
+}
+
+/* centre-to-centre distances to the previous and next column (row) */
+static double HXM(const grid_t* g, int i) { return 0.5 * (WX(g, i - 1) + WX(g, i)); }
+static double HXP(const grid_t* g, int i) { return 0.5 * (WX(g, i) + WX(g, i + 1)); }
+static double HYM(const grid_t* g, int j) { return 0.5 * (WY(g, j - 1) + WY(g, j)); }
+static double HYP(const grid_t* g, int j) { return 0.5 * (WY(g, j) + WY(g, j + 1)); }
 
 /* Closure, properties, mu_c and gradients on the whole ghosted grid (steps
  * (2) and (6) of Sec. 2.5 need them at every stage). */
@@ -363,7 +454,6 @@ static void derive_all(grid_t* g)
     int nx = g->nx, ny = g->ny;
     double beta = 12.0 * P->sigma / P->xi;
     double kappa = 1.5 * P->xi * P->sigma;
-    double idx2 = 1.0 / (P->dx * P->dx);
 #pragma omp parallel for schedule(static)
     for (int j = -NG; j < ny + NG; ++j)
         for (int i = -NG; i < nx + NG; ++i) derive(P, at(g, i, j));
@@ -372,18 +462,19 @@ static void derive_all(grid_t* g)
     for (int j = -2; j < ny + 2; ++j)
         for (int i = -2; i < nx + 2; ++i) {
             double C = at(g, i, j)->W[4];
-            double lap = (at(g, i + 1, j)->W[4] + at(g, i - 1, j)->W[4] + at(g, i, j + 1)->W[4] +
-                          at(g, i, j - 1)->W[4] - 4.0 * C) * idx2;
+            double lap = d2(HXM(g, i), HXP(g, i), at(g, i - 1, j)->W[4], C, at(g, i + 1, j)->W[4]) +
+                         d2(HYM(g, j), HYP(g, j), at(g, i, j - 1)->W[4], C, at(g, i, j + 1)->W[4]);
             at(g, i, j)->val[V_MUC] = 2.0 * beta * C * (C - 1.0) * (2.0 * C - 1.0) - kappa * lap;
         }
-    /* central gradients (R8) on interior + 1 ghost layer */
-    double i2dx = 1.0 / (2.0 * P->dx);
+    /* gradients (R8) on interior + 1 ghost layer */
 #pragma omp parallel for schedule(static)
     for (int j = -1; j < ny + 1; ++j)
         for (int i = -1; i < nx + 1; ++i)
             for (int v = 0; v < NV; ++v) {
-                at(g, i, j)->grad[v][0] = (at(g, i + 1, j)->val[v] - at(g, i - 1, j)->val[v]) * i2dx;
-                at(g, i, j)->grad[v][1] = (at(g, i, j + 1)->val[v] - at(g, i, j - 1)->val[v]) * i2dx;
+                at(g, i, j)->grad[v][0] = d1(HXM(g, i), HXP(g, i), at(g, i - 1, j)->val[v], at(g, i, j)->val[v],
+                                             at(g, i + 1, j)->val[v]);
+                at(g, i, j)->grad[v][1] = d1(HYM(g, j), HYP(g, j), at(g, i, j - 1)->val[v], at(g, i, j)->val[v],
+                                             at(g, i, j + 1)->val[v]);
             }
 }
 
@@ -394,20 +485,22 @@ static void reconstruct(const cell_t* c, double rx, double ry, double out[NV])
 }
 
 /* Fluxes of Eq. (53) through the face between cell a (left or below) and
- * cell b (right or above).  dir 0: x-face (n = +x); dir 1: y-face (n = +y). */
-static void face_flux(const or_params* P, const cell_t* a, const cell_t* b, int dir, double F[5])
+ * cell b (right or above).  dir 0: x-face (n = +x); dir 1: y-face (n = +y).
+ * The face centre lies half_a from the centre of a and half_b from that of b
+ * (half the cells' widths along n, R24). */
+static void face_flux(const or_params* P, const cell_t* a, const cell_t* b, int dir, double half_a, double half_b,
+                      double F[5])
 {
     const int Qhg = P->lattice_hg == 5 ? 5 : 9;
     const double* Whg = Qhg == 5 ? Q5_W : Q9_W;
     const double cpref = 0.5 * (P->cp[0] + P->cp[1]); /* R6 */
     const double dt = P->delta_t;
-    const double half = 0.5 * P->dx;
     const int nxn = dir == 0 ? 1 : 0, nyn = dir == 0 ? 0 : 1;
 
     /* old-level face state: average of both extrapolations to the face centre */
     double ra[NV], rb[NV], avg[NV];
-    reconstruct(a, half * nxn, half * nyn, ra);
-    reconstruct(b, -half * nxn, -half * nyn, rb);
+    reconstruct(a, half_a * nxn, half_a * nyn, ra);
+    reconstruct(b, -half_b * nxn, -half_b * nyn, rb);
     for (int v = 0; v < NV; ++v) avg[v] = 0.5 * (ra[v] + rb[v]);
     double Cf = clamp01(avg[V_C]), Fsf = clamp01(avg[V_FS]);
     double rho_f = mix(P->rho, Cf, Fsf);
@@ -424,13 +517,13 @@ static void face_flux(const or_params* P, const cell_t* a, const cell_t* b, int 
         int side = ex * nxn + ey * nyn; /* e_alpha . n */
         double psi[NV];
         if (side > 0) {
-            reconstruct(a, half * nxn - ex * dt, half * nyn - ey * dt, psi);
+            reconstruct(a, half_a * nxn - ex * dt, half_a * nyn - ey * dt, psi);
         } else if (side < 0) {
-            reconstruct(b, -half * nxn - ex * dt, -half * nyn - ey * dt, psi);
+            reconstruct(b, -half_b * nxn - ex * dt, -half_b * nyn - ey * dt, psi);
         } else {
             double pa[NV], pb[NV];
-            reconstruct(a, half * nxn - ex * dt, half * nyn - ey * dt, pa);
-            reconstruct(b, -half * nxn - ex * dt, -half * nyn - ey * dt, pb);
+            reconstruct(a, half_a * nxn - ex * dt, half_a * nyn - ey * dt, pa);
+            reconstruct(b, -half_b * nxn - ex * dt, -half_b * nyn - ey * dt, pb);
             for (int v = 0; v < NV; ++v) psi[v] = 0.5 * (pa[v] + pb[v]);
         }
         double Cc = clamp01(psi[V_C]), Fs = clamp01(psi[V_FS]);
@@ -507,8 +600,9 @@ static void wall_face(const or_params* P, int side, double F[5])
 }
 
 /* Residual R(W) of Eq. (57) on the interior; W and R are 5 planes of nx*ny
- * (row-major, x fastest).  Fx: 5 planes of (nx+1)*ny (face i at x = i dx),
- * Fy: 5 planes of nx*(ny+1) (face j at y = j dx); either may be NULL. */
+ * (row-major, x fastest).  Fx: 5 planes of (nx+1)*ny (face i on the left of
+ * column i), Fy: 5 planes of nx*(ny+1) (face j below row j); either may be
+ * NULL. */
 static void residual(grid_t* g, const double* Fsdot, double* R, double* Fx, double* Fy)
 {
     const or_params* P = g->P;
@@ -522,7 +616,7 @@ static void residual(grid_t* g, const double* Fsdot, double* R, double* Fx, doub
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i <= nx; ++i) {
             double F[5];
-            face_flux(P, at(g, i - 1, j), at(g, i, j), 0, F);
+            face_flux(P, at(g, i - 1, j), at(g, i, j), 0, 0.5 * WX(g, i - 1), 0.5 * WX(g, i), F);
             if (i == 0) wall_face(P, 0, F);
             if (i == nx) wall_face(P, 1, F);
             for (int k = 0; k < 5; ++k) fx[k * nfx + (size_t)j * (nx + 1) + i] = F[k];
@@ -531,13 +625,12 @@ static void residual(grid_t* g, const double* Fsdot, double* R, double* Fx, doub
     for (int j = 0; j <= ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double F[5];
-            face_flux(P, at(g, i, j - 1), at(g, i, j), 1, F);
+            face_flux(P, at(g, i, j - 1), at(g, i, j), 1, 0.5 * WY(g, j - 1), 0.5 * WY(g, j), F);
             if (j == 0) wall_face(P, 2, F);
             if (j == ny) wall_face(P, 3, F);
             for (int k = 0; k < 5; ++k) fy[k * nfy + (size_t)j * nx + i] = F[k];
         }
     const double ratio = P->rho[0] / P->rho[1]; /* rho_s / rho_l */
-    const double i2dx = 1.0 / (2.0 * P->dx);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -545,8 +638,8 @@ static void residual(grid_t* g, const double* Fsdot, double* R, double* Fx, doub
             double fs_dot = Fsdot ? Fsdot[(size_t)j * nx + i] : 0.0;
             double u = c->val[V_U], v = c->val[V_V], C = c->W[4];
             double div_u = c->grad[V_U][0] + c->grad[V_V][1];
-            double drho_x = (at(g, i + 1, j)->rho - at(g, i - 1, j)->rho) * i2dx;
-            double drho_y = (at(g, i, j + 1)->rho - at(g, i, j - 1)->rho) * i2dx;
+            double drho_x = d1(HXM(g, i), HXP(g, i), at(g, i - 1, j)->rho, c->rho, at(g, i + 1, j)->rho);
+            double drho_y = d1(HYM(g, j), HYP(g, j), at(g, i, j - 1)->rho, c->rho, at(g, i, j + 1)->rho);
             double surf = P->surf_model == 1 ? -c->Fl * C : -C; /* F_surf = surf * grad mu_c */
             double S[5];
             S[0] = c->cp * c->val[V_T] * div_u;                                   /* Eq. 51 row 1 */
@@ -557,8 +650,8 @@ static void residual(grid_t* g, const double* Fsdot, double* R, double* Fx, doub
             for (int k = 0; k < 5; ++k) {
                 double dfx = fx[k * nfx + (size_t)j * (nx + 1) + i + 1] - fx[k * nfx + (size_t)j * (nx + 1) + i];
                 double dfy = fy[k * nfy + (size_t)(j + 1) * nx + i] - fy[k * nfy + (size_t)j * nx + i];
-                /* Eq. (52) on a uniform Cartesian cell: V = dx^2, S_ij = dx */
-                R[k * nc + (size_t)j * nx + i] = -dfx / P->dx - dfy / P->dx + S[k];
+                /* Eq. (52) on a Cartesian cell: V = w_i h_j, S = h_j (x faces), w_i (y faces) */
+                R[k * nc + (size_t)j * nx + i] = -dfx / WX(g, i) - dfy / WY(g, j) + S[k];
             }
         }
     if (Fx) memcpy(Fx, fx, 5 * nfx * sizeof(double));
@@ -588,10 +681,25 @@ static void project(const or_params* P, double* W)
 /* ---------------------------------------------------------------------------
  * Public entry points.
  * ------------------------------------------------------------------------- */
+/* smallest width of n cells (dx where the array is NULL); 0 if one is not a
+ * finite positive number */
+static double min_width(const double* w, double dx, int n)
+{
+    if (!w) return dx;
+    double m = w[0];
+    for (int i = 0; i < n; ++i) {
+        if (!(w[i] > 0.0) || !isfinite(w[i])) return 0.0;
+        if (w[i] < m) m = w[i];
+    }
+    return m;
+}
+
 static int check(const or_params* P)
 {
     if (!P || P->nx < 1 || P->ny < 1 || P->dx <= 0.0) return OR_EINVAL;
-    if (P->delta_t <= 0.0 || P->delta_t > 0.5 * P->dx + 1e-15) return OR_EINVAL;
+    double wmin = fmin(min_width(P->xw, P->dx, P->nx), min_width(P->yw, P->dx, P->ny));
+    if (!(wmin > 0.0)) return OR_EINVAL;
+    if (P->delta_t <= 0.0 || P->delta_t > 0.5 * wmin * (1.0 + 1e-15)) return OR_EINVAL;
     if (P->lattice_hg != 5 && P->lattice_hg != 9) return OR_EINVAL;
     if (P->bc[0].periodic != P->bc[1].periodic || P->bc[2].periodic != P->bc[3].periodic) return OR_EINVAL;
     if (!P->bc[0].periodic && P->nx < NG) return OR_EINVAL;
@@ -722,9 +830,10 @@ int or_diagnostics(const or_params* P, const double* W, double* out)
 {
     if (check(P)) return OR_EINVAL;
     size_t n = (size_t)P->nx * P->ny;
-    double dV = P->dx * P->dx;
     double s_rho = 0, s_c = 0, s_h = 0, s_fs = 0, umax = 0;
     for (size_t q = 0; q < n; ++q) {
+        int i = (int)(q % (size_t)P->nx), j = (int)(q / (size_t)P->nx);
+        double dV = (P->xw ? P->xw[i] : P->dx) * (P->yw ? P->yw[j] : P->dx); /* R24 */
         double H = W[q], C = W[4 * n + q];
         double Fl, T;
         or_closure(P, H, C, &Fl, &T);

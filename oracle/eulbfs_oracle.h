@@ -39,6 +39,10 @@ typedef struct {
     double sigma, xi, mobility, Qg;
     double gx, gy;
     or_bc bc[4]; /* x-, x+, y-, y+ */
+    /* Stretched mesh (R24): nx column widths and ny row heights, or NULL for
+     * the uniform spacing dx in that direction. */
+    const double* xw;
+    const double* yw;
 } or_params;
 
 void or_closure(const or_params* P, double H, double C, double* Fl, double* T);

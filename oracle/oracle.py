@@ -42,6 +42,7 @@ class _Params(ct.Structure):
         ("sigma", ct.c_double), ("xi", ct.c_double), ("mobility", ct.c_double), ("Qg", ct.c_double),
         ("gx", ct.c_double), ("gy", ct.c_double),
         ("bc", _BC * 4),
+        ("xw", ct.POINTER(ct.c_double)), ("yw", ct.POINTER(ct.c_double)),
     ]
 
 
@@ -94,6 +95,15 @@ def params(pr) -> _Params:
             P.bc[k].flow, P.bc[k].heat = w.flow, w.heat
             P.bc[k].T_w, P.bc[k].theta_deg = w.T_w, w.theta_deg
             P.bc[k].theta_adv, P.bc[k].theta_rec = w.theta_adv, w.theta_rec
+    # stretched mesh (R24): the arrays stay referenced by the struct
+    P._widths = []
+    for name, src, n in (("xw", pr.x_width, pr.nx), ("yw", pr.y_width, pr.ny)):
+        if src is not None:
+            a = np.ascontiguousarray(src, dtype=np.float64)
+            if a.shape != (n,):
+                raise ValueError(f"{name}: expected {n} widths, got shape {a.shape}")
+            P._widths.append(a)
+            setattr(P, name, a.ctypes.data_as(ct.POINTER(ct.c_double)))
     return P
 
 

@@ -71,6 +71,9 @@ class Problem:
     periodic_y: bool = False
     walls: Dict[str, Wall] = field(default_factory=dict)
     precision: int = 0  # 0: FP64; 1: FP32 fields and fluxes with FP64 enthalpy
+    # stretched mesh: nx column widths and ny row heights (None: uniform dx)
+    x_width: Optional[np.ndarray] = None
+    y_width: Optional[np.ndarray] = None
 
     def wall(self, side: str) -> Optional[Wall]:
         periodic = self.periodic_x if side[0] == "x" else self.periodic_y
@@ -101,10 +104,29 @@ class InitialState:
         return [np.ascontiguousarray(a, dtype=np.float64) for a in (self.T, self.Fl, self.C, self.u, self.v, self.p)]
 
 
+def widths(pr: Problem):
+    """Column widths and row heights, (nx,) and (ny,) float64."""
+    wx = np.full(pr.nx, pr.dx) if pr.x_width is None else np.asarray(pr.x_width, dtype=np.float64)
+    wy = np.full(pr.ny, pr.dx) if pr.y_width is None else np.asarray(pr.y_width, dtype=np.float64)
+    return wx, wy
+
+
+def centres_1d(w: np.ndarray) -> np.ndarray:
+    """Cell centres of a row of cells with widths w, the first face at 0."""
+    return np.cumsum(w) - 0.5 * w
+
+
 def cell_centres(pr: Problem):
-    x = (np.arange(pr.nx) + 0.5) * pr.dx
-    y = (np.arange(pr.ny) + 0.5) * pr.dx
-    return np.meshgrid(x, y)  # (ny, nx) each
+    wx, wy = widths(pr)
+    return np.meshgrid(centres_1d(wx), centres_1d(wy))  # (ny, nx) each
+
+
+def graded_widths(n: int, w0: float, growth: float, w_max: float, both_ends: bool = False) -> np.ndarray:
+    """n widths growing geometrically by `growth` from w0 at the start (and at
+    the end too with both_ends) up to w_max: a mesh refined towards a wall."""
+    i = np.arange(n, dtype=np.float64)
+    d = np.minimum(i, n - 1 - i) if both_ends else i
+    return np.minimum(w0 * growth ** d, w_max)
 
 
 def layer_profile(coord: np.ndarray, H0: float, xi: float) -> np.ndarray:

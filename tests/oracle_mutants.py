@@ -2,7 +2,7 @@
 
 Each entry plants one plausible mistake in a copy of oracle/eulbfs_oracle.c
 (a flipped sign, a dropped term, a swapped index or operand), builds it, and
-runs tests/test_oracle_pins.py against it.  Every mutant must make at least
+runs tests/test_oracle_pins.py and tests/test_oracle_mesh.py against it.  Every mutant must make at least
 one pin fail.
 
     python tests/oracle_mutants.py [name ...]
@@ -10,6 +10,17 @@ one pin fail.
 import os, shutil, subprocess, sys, tempfile
 SRC = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 MUTS = {
+ 'mesh_d1_central': ('return (hm * hm * (vp - v0) + hp * hp * (v0 - vm)) / (hm * hp * (hm + hp));', 'return (vp - vm) / (hm + hp);'),
+ 'mesh_d2_width': ('return 2.0 * ((vp - v0) / hp - (v0 - vm) / hm) / (hm + hp);', 'return ((vp - v0) / hp - (v0 - vm) / hm) / hm;'),
+ 'mesh_hxm': ('return 0.5 * (WX(g, i - 1) + WX(g, i)); }', 'return 0.5 * (WX(g, i + 1) + WX(g, i)); }'),
+ 'mesh_half_swap': ('0.5 * WX(g, i - 1), 0.5 * WX(g, i), F);', '0.5 * WX(g, i), 0.5 * WX(g, i - 1), F);'),
+ 'mesh_residual_width': ('-dfx / WX(g, i) - dfy / WY(g, j)', '-dfx / WX(g, i + 1) - dfy / WY(g, j)'),
+ 'mesh_face_area': ('-dfx / WX(g, i) - dfy / WY(g, j)', '-dfx / WY(g, j) - dfy / WX(g, i)'),
+ 'mesh_ghost_width': ('src = i < 0 ? -i - 1 : 2 * n - 1 - i;', 'src = i < 0 ? 0 : n - 1;'),
+ 'mesh_wall_distance': ('double d = 2.0 * s[k - 1];', 'double d = (2 * k - 1) * s[0] * 2.0;'),
+ 'mesh_wall_far_end': ('side == 1 ? WX(g, g->nx - 1 - m)', 'side == 1 ? WX(g, m)'),
+ 'mesh_lagrange': ('double l1 = -(s[0] + s[2]) / ((s[1] - s[0]) * (s[1] - s[2]));', 'double l1 = -(s[0] + s[2]) / ((s[1] - s[0]) * (s[2] - s[1]));'),
+ 'mesh_dV_swap': ('double dV = (P->xw ? P->xw[i] : P->dx) * (P->yw ? P->yw[j] : P->dx);', 'double dV = (P->xw ? P->xw[j % P->nx] : P->dx) * (P->yw ? P->yw[i % P->ny] : P->dx);'),
  'fstar_sign': ('(1.0 - 1.0 / (2.0 * tau_f)) * fneqm', '-(1.0 - 1.0 / (2.0 * tau_f)) * fneqm'),
  'kappa_sign': ('- kappa * lap', '+ kappa * lap'),
  'gamma_one': ('double Gamma = CS2 * (eu / CS2', 'double Gamma = CS2 * (1.0 + eu / CS2'),
@@ -79,7 +90,7 @@ for name, spec in MUTS.items():
         s = s.replace(a, b, 1)
     open(p,'w').write(s)
     subprocess.run(['gcc','-O2','-fopenmp','-ffp-contract=off','-fPIC','-shared','-o',d+'/oracle/liboracle.so',p,'-lm'],check=True)
-    r=subprocess.run([sys.executable,'-m','pytest','-q','-x','--timeout','120','tests/test_oracle_pins.py','-p','no:cacheprovider'],cwd=d,capture_output=True,text=True)
+    r=subprocess.run([sys.executable,'-m','pytest','-q','-x','--timeout','120','tests/test_oracle_pins.py','tests/test_oracle_mesh.py','-p','no:cacheprovider'],cwd=d,capture_output=True,text=True)
     last=[l for l in r.stdout.splitlines() if 'FAILED' in l or 'passed' in l or 'failed' in l]
     res[name]='caught' if r.returncode!=0 else 'SURVIVED'
     print(name, res[name], last[:1], flush=True)
