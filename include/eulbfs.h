@@ -18,7 +18,9 @@
  *   - Lattice units: cell size dx (default 1), c_s^2 = 1/3, streaming step
  *     delta_t with 0 < delta_t <= dx/2, fixed update step dt.
  *   - Fields are planes of nx*ny values, row-major, x fastest (index
- *     j*nx + i, cell centre ((i+1/2) dx, (j+1/2) dx)).
+ *     j*nx + i, cell centre ((i+1/2) dx, (j+1/2) dx) on a uniform mesh).
+ *   - Stretched meshes: optional column widths and row heights (see
+ *     eulbfs_params.x_width) make the mesh a tensor product of unequal cells.
  *   - Every function returns EULBFS_OK (0) or a negative status; the text of
  *     the last failure is returned by eulbfs_last_error().
  *   - A handle is used by one host thread at a time.  All device work is
@@ -40,7 +42,7 @@
 extern "C" {
 #endif
 
-#define EULBFS_ABI_VERSION 2u
+#define EULBFS_ABI_VERSION 3u
 
 /* status codes */
 #define EULBFS_OK 0
@@ -66,7 +68,8 @@ extern "C" {
 #define EULBFS_KERNEL_SPLIT 1 /* ghost fill, primitives, face fluxes, update apart */
 #define EULBFS_KERNEL_AUTO 2  /* FUSED with the tile shape that create timed
                                  fastest on the initial state (cached per
-                                 process for the grid, precision and lattice) */
+                                 process for the grid, precision and lattice);
+                                 SPLIT on a stretched mesh */
 
 /* One side of the domain.  Sides are indexed 0: x-, 1: x+, 2: y-, 3: y+.
  * periodic must agree on opposite sides.  For a wall:
@@ -138,8 +141,26 @@ typedef struct {
     eulbfs_bc bc[4];
     int32_t tile_x, tile_y; /* fused-kernel tile (32x8, 64x4, 16x16, 64x8,
                                32x16, 32x32); 0 picks 32x8; AUTO ignores it */
-    int32_t reserved[6];
+    const double* x_width;  /* host array of nx column widths, or NULL: dx     */
+    const double* y_width;  /* host array of ny row heights, or NULL: dx       */
+    int32_t reserved[2];
 } eulbfs_params;
+/* Stretched meshes (Eq. 52 holds for any cell; the paper runs uniform ones).
+ * With x_width or y_width set the mesh is the tensor product of those cells:
+ * column i spans [sum_{m<i} w_m, sum_{m<=i} w_m], V = w_i h_j, S = h_j on x
+ * faces and w_i on y faces.  Gradients and lap(C) are the derivatives of the
+ * parabola through a cell centre and its two neighbours (the central
+ * differences of a uniform mesh); Eq. (54) extrapolates from each cell by its
+ * own half width to the face; one delta_t for the whole mesh, at most half
+ * the smallest width.  Ghost cells take the width of the cell they copy, so a
+ * wall lies midway between a ghost and its mirror: the wetting offset uses
+ * the distance between them in place of (2k - 1) dx, and the hysteresis
+ * angle reads dC/dn from the parabola through the first three cell centres.
+ * Widths must be finite and > 0; both arrays are copied by eulbfs_create and
+ * may be freed afterwards.  Such a mesh runs on the split kernels: kernel
+ * AUTO selects them, FUSED returns EULBFS_ENOTSUP, and the batch API refuses
+ * it (EULBFS_ENOTSUP; eulbfs_batch_request_bytes returns 0).  Diagnostic
+ * integrals weight each cell by w_i h_j and the tip height by h_j. */
 
 /* Initial state. */
 #define EULBFS_INIT_PRIMITIVE 0 /* 6 planes: T, F_l, C, u, v, p                */

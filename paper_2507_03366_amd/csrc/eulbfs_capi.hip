@@ -40,6 +40,20 @@ int set_err(std::string* where, int code, const std::string& msg)
             return set_err(err, EULBFS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
     } while (0)
 
+bool stretched(const eulbfs_params* p) { return p->x_width != nullptr || p->y_width != nullptr; }
+
+// Smallest of n widths (dx for a NULL array); 0 if one is not finite and > 0.
+double min_width(const double* w, double dx, int n)
+{
+    if (!w) return dx;
+    double m = w[0];
+    for (int i = 0; i < n; ++i) {
+        if (!(w[i] > 0) || !std::isfinite(w[i])) return 0.0;
+        m = std::min(m, w[i]);
+    }
+    return m;
+}
+
 std::string check(const eulbfs_params* p)
 {
     if (!p) return "params is NULL";
@@ -48,8 +62,11 @@ std::string check(const eulbfs_params* p)
     if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
     if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return "grid too large";
     if (!(p->dx > 0)) return "dx must be > 0";
-    if (!(p->delta_t > 0) || p->delta_t > 0.5 * p->dx * (1 + 1e-12))
-        return "delta_t must satisfy 0 < delta_t <= dx/2 (surrounding points inside the two cells)";
+    const double wmin = std::min(min_width(p->x_width, p->dx, p->nx), min_width(p->y_width, p->dx, p->ny));
+    if (!(wmin > 0)) return "cell widths must be finite and > 0";
+    if (!(p->delta_t > 0) || p->delta_t > 0.5 * wmin * (1 + 1e-12))
+        return "delta_t must satisfy 0 < delta_t <= half the smallest cell width (surrounding points inside the "
+               "two cells)";
     if (!(p->dt > 0)) return "dt must be > 0";
     if (p->lattice_hg != 5 && p->lattice_hg != 9) return "lattice_hg must be 5 or 9";
     if (p->precision != EULBFS_FP64 && p->precision != EULBFS_FP32) return "unknown precision";
@@ -157,6 +174,9 @@ DevParams make_dev(const eulbfs_params* p)
 
 // Byte offsets of every region of a solver's workspace.
 struct Layout {
+    size_t mesh;         // stretched-mesh tables (mesh_bytes; 0 on a uniform mesh)
+    size_t mesh_bytes;
+    int msx, msy;        // ghosted columns / rows per table, padded
     size_t state_bytes;  // one copy of W
     size_t plane_R, plane_H;
     size_t W0, fsdot, WA, WB, staging, staging_bytes, red_partial, red_out;
@@ -195,7 +215,8 @@ Layout make_layout(const eulbfs_params* p)
     off += align_up((size_t)L.red_blocks * NRED * 8);
     L.red_out = off;
     off += align_up(16 * 8);
-    L.split = p->kernel == EULBFS_KERNEL_SPLIT;
+    // a stretched mesh runs on the split kernels (AUTO picks them; FUSED is refused at create)
+    L.split = p->kernel == EULBFS_KERNEL_SPLIT || (stretched(p) && p->kernel == EULBFS_KERNEL_AUTO);
     L.gpitch = round_pitch(p->nx + 2 * NG);
     L.fpitch = round_pitch(p->nx + 1);
     L.gplane_H = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * 8);  // H and C planes
@@ -212,8 +233,80 @@ Layout make_layout(const eulbfs_params* p)
         L.Fy = off;
         off += 5 * L.fstride * rs;
     }
+    if (stretched(p)) {
+        L.msx = (p->nx + 2 * NG + 31) / 32 * 32;
+        L.msy = (p->ny + 2 * NG + 31) / 32 * 32;
+        L.mesh_bytes = align_up(((size_t)4 * MS_STRIDE + (size_t)NMESH * (L.msx + L.msy)) * 8);
+        L.mesh = off;
+        off += L.mesh_bytes;
+    }
     L.total = off;
     return L;
+}
+
+// Geometry tables of a stretched mesh (layout of MESH_* and MS_* in the
+// device header): mside[4][MS_STRIDE], then NMESH arrays of L.msx doubles
+// over the ghosted columns, then NMESH arrays of L.msy over the ghosted rows.
+// Ghost cells take the width of the cell they copy (the periodic image, or
+// the interior cell k-1 that ghost layer k mirrors), so a wall lies midway
+// between a ghost and its mirror.
+std::vector<double> mesh_tables(const eulbfs_params* p, const Layout& L)
+{
+    std::vector<double> t((size_t)4 * MS_STRIDE + (size_t)NMESH * (L.msx + L.msy), 0.0);
+    auto ghosted = [&](const double* w, int n, bool periodic) {
+        std::vector<double> g(n + 2 * NG);
+        for (int l = 0; l < n + 2 * NG; ++l) {
+            const int i = l - NG;
+            int src = i;
+            if (i < 0 || i >= n) src = periodic ? (i % n + n) % n : (i < 0 ? -i - 1 : 2 * n - 1 - i);
+            g[l] = w ? w[src] : p->dx;
+        }
+        return g;
+    };
+    auto fill = [&](const std::vector<double>& g, double* m, int stride) {
+        const int gn = (int)g.size();
+        for (int l = 0; l < gn; ++l) {
+            m[MESH_HW * stride + l] = 0.5 * g[l];
+            m[MESH_IW * stride + l] = 1.0 / g[l];
+            if (l == 0 || l == gn - 1) continue;
+            const double hm = 0.5 * (g[l - 1] + g[l]), hp = 0.5 * (g[l] + g[l + 1]), hs = hm + hp;
+            // parabola through the centres at -hm, 0, +hp
+            m[MESH_GM * stride + l] = -hp / (hm * hs);
+            m[MESH_G0 * stride + l] = (hp - hm) / (hm * hp);
+            m[MESH_GP * stride + l] = hm / (hp * hs);
+            m[MESH_LM * stride + l] = 2.0 / (hm * hs);
+            m[MESH_LP * stride + l] = 2.0 / (hp * hs);
+            m[MESH_L0 * stride + l] = -(m[MESH_LM * stride + l] + m[MESH_LP * stride + l]);
+        }
+    };
+    const std::vector<double> gx = ghosted(p->x_width, p->nx, p->bc[0].periodic != 0);
+    const std::vector<double> gy = ghosted(p->y_width, p->ny, p->bc[2].periodic != 0);
+    double* mx = t.data() + 4 * MS_STRIDE;
+    double* my = mx + (size_t)NMESH * L.msx;
+    fill(gx, mx, L.msx);
+    fill(gy, my, L.msy);
+    for (int sd = 0; sd < 4; ++sd) {
+        const eulbfs_bc& b = p->bc[sd];
+        double* ms = t.data() + sd * MS_STRIDE;
+        if (b.periodic) continue;
+        // centres of the first three interior cells, measured from the wall
+        const std::vector<double>& g = sd < 2 ? gx : gy;
+        const int n = sd < 2 ? p->nx : p->ny;
+        double s[3], acc = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            const double w = g[NG + ((sd & 1) ? n - 1 - m : m)];
+            s[m] = acc + 0.5 * w;
+            acc += w;
+        }
+        for (int k = 0; k < 3; ++k) ms[MS_D + k] = 2.0 * s[k];
+        // d/ds at s = 0 of the Lagrange parabola through the three centres
+        ms[MS_L0 + 0] = -(s[1] + s[2]) / ((s[0] - s[1]) * (s[0] - s[2]));
+        ms[MS_L0 + 1] = -(s[0] + s[2]) / ((s[1] - s[0]) * (s[1] - s[2]));
+        ms[MS_L0 + 2] = -(s[0] + s[1]) / ((s[2] - s[0]) * (s[2] - s[1]));
+        ms[MS_K] = 4.0 / p->xi;
+        ms[MS_WET] = ms[MS_K] * std::cos(b.theta_deg * M_PI / 180.0);
+    }
+    return t;
 }
 
 size_t split_scratch_bytes(const Layout& L, size_t rs)
@@ -391,14 +484,16 @@ int do_init(eulbfs_solver* h, const eulbfs_init* init, bool sync = true)
 // The EULBFS_SCALAR_DIAG record from the raw reduction sums.
 void diag_from_sums(const eulbfs_solver* h, const double r[NRED], double* out)
 {
-    const double dV = h->prm.dx * h->prm.dx;
+    // a stretched mesh weights each cell inside the sums
+    const bool nu = h->dp.mside != nullptr;
+    const double dV = nu ? 1.0 : h->prm.dx * h->prm.dx;
     out[0] = r[0] * dV;
     out[1] = r[1] * dV;
     out[2] = r[2] * dV;
     out[3] = r[3] * dV;
     out[4] = r[4];
     out[5] = r[5];
-    out[6] = r[6] * h->prm.dx;
+    out[6] = nu ? r[6] : r[6] * h->prm.dx;
     out[7] = (double)h->steps * h->prm.dt;
     out[8] = (double)h->steps;
     out[9] = h->prm.dt;
@@ -595,7 +690,11 @@ int autotune(eulbfs_solver* h, const eulbfs_init* init)
 template <typename R>
 int setup_schedule(eulbfs_solver* h, const eulbfs_init* init)
 {
-    h->sched = h->prm.kernel == EULBFS_KERNEL_SPLIT ? EULBFS_KERNEL_SPLIT : EULBFS_KERNEL_FUSED;
+    if (h->L.split) {  // SPLIT, or a stretched mesh
+        h->sched = EULBFS_KERNEL_SPLIT;
+        return EULBFS_OK;
+    }
+    h->sched = EULBFS_KERNEL_FUSED;
     if (h->prm.kernel == EULBFS_KERNEL_AUTO) return autotune<R>(h, init);
     return EULBFS_OK;
 }
@@ -627,6 +726,8 @@ size_t eulbfs_workspace_bytes(const eulbfs_params* prm)
 
 namespace {
 
+void free_solver(eulbfs_solver* h, bool sync);
+
 // eulbfs_create; with sync = false the initial state is only enqueued.
 int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes, void* hip_stream,
                   bool sync, eulbfs_solver** out)
@@ -639,11 +740,15 @@ int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
     if (!init || !init->planes) return set_err(err, EULBFS_EINVAL, "init or init->planes is NULL");
     if (init->kind != EULBFS_INIT_PRIMITIVE && init->kind != EULBFS_INIT_CONSERVED)
         return set_err(err, EULBFS_EINVAL, "unknown init kind");
+    if (stretched(prm) && prm->kernel == EULBFS_KERNEL_FUSED)
+        return set_err(err, EULBFS_ENOTSUP, "stretched meshes run on the split kernels (kernel SPLIT or AUTO)");
     const Layout L = make_layout(prm);
     if (d_ws && ws_bytes < L.total) return set_err(err, EULBFS_ENOMEM, "workspace smaller than eulbfs_workspace_bytes()");
     if (d_ws && ((uintptr_t)d_ws % ALIGN) != 0) return set_err(err, EULBFS_EINVAL, "workspace must be 256-byte aligned");
     eulbfs_solver* h = new eulbfs_solver();
     h->prm = *prm;
+    h->prm.x_width = nullptr;  // the caller's arrays live on in the mesh tables only
+    h->prm.y_width = nullptr;
     h->dp = make_dev(prm);
     h->L = L;
     h->stream = (hipStream_t)hip_stream;
@@ -657,6 +762,20 @@ int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
             return set_err(err, EULBFS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(he));
         }
         h->own_ws = true;
+    }
+    if (L.mesh_bytes) {
+        const std::vector<double> t = mesh_tables(prm, L);
+        hipError_t he = hipMemcpy(h->ws + L.mesh, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (he != hipSuccess) {
+            free_solver(h, false);
+            return set_err(err, EULBFS_EDEVICE, std::string("hipMemcpy (mesh tables): ") + hipGetErrorString(he));
+        }
+        const double* base = (const double*)(h->ws + L.mesh);
+        h->dp.mside = base;
+        h->dp.mxc = base + 4 * MS_STRIDE;
+        h->dp.myc = h->dp.mxc + (size_t)NMESH * L.msx;
+        h->dp.msx = L.msx;
+        h->dp.msy = L.msy;
     }
     int rc = prm->precision == EULBFS_FP32 ? do_init<float>(h, init, sync) : do_init<double>(h, init, sync);
     if (rc == EULBFS_OK)
@@ -1040,7 +1159,7 @@ extern "C" {
 
 size_t eulbfs_batch_request_bytes(const eulbfs_params* prm)
 {
-    if (!check(prm).empty()) return 0;
+    if (!check(prm).empty() || stretched(prm)) return 0;
     const eulbfs_params p = batch_view(prm);
     return align_up(make_layout(&p).total);
 }
@@ -1120,6 +1239,7 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
     *slot = -1;
     const std::string e = check(prm);
     if (!e.empty()) return set_err(err, EULBFS_EINVAL, e);
+    if (stretched(prm)) return set_err(err, EULBFS_ENOTSUP, "the batch runs uniform meshes only");
     if (prm->precision != b->precision) return set_err(err, EULBFS_EINVAL, "request precision differs from the batch");
     if (nsteps <= 0) return set_err(err, EULBFS_EINVAL, "nsteps must be > 0");
     int k = 0;

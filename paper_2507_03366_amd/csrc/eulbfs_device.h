@@ -52,7 +52,27 @@ struct DevParams {
     // FAST_UCP closure constants: H_s = C_p T_s, H_l = C_p T_l + L, 1/C_p,
     // 1/(H_l - H_s) (0 without a mushy range)
     double Hs_u, Hl_u, inv_cp, inv_dH;
+    // Stretched tensor-product mesh (split kernels only); all NULL on a
+    // uniform mesh.  mside: per side, MS_STRIDE doubles (MS_*).  mxc, myc:
+    // NMESH arrays (MESH_*) over the ghosted columns / rows, msx / msy apart.
+    const double* mside;
+    const double* mxc;
+    const double* myc;
+    int msx, msy;
 };
+
+// Per-cell mesh coefficients along one direction, at ghosted index l:
+//   MESH_GM, MESH_G0, MESH_GP  d psi/ds = GM psi_{l-1} + G0 psi_l + GP psi_{l+1}
+//                              (derivative of the parabola through the three
+//                              centres; (psi_{l+1} - psi_{l-1}) / (2 dx) when uniform)
+//   MESH_LM, MESH_L0, MESH_LP  d2 psi/ds2 of the same parabola
+//   MESH_HW                    half width of the cell
+//   MESH_IW                    1 / width
+enum { MESH_GM = 0, MESH_G0, MESH_GP, MESH_LM, MESH_L0, MESH_LP, MESH_HW, MESH_IW, NMESH };
+// Per wall side: MS_D + k - 1 distance between the centres of ghost layer k
+// and its mirror cell; MS_L0..2 weights of dC/dn at the wall from the first
+// three interior cells; MS_WET (4/xi) cos(theta); MS_K 4/xi.
+enum { MS_D = 0, MS_L0 = 3, MS_WET = 6, MS_K = 7, MS_STRIDE = 8 };
 
 // Fast paths compiled as template flags.  Each computes the same quantities
 // as the general code (equal up to rounding order), with fewer operations:
@@ -220,10 +240,24 @@ __device__ __forceinline__ double wet_factor(const DevParams& P, int side, doubl
     return P.wet_k * c;
 }
 
+// Stretched mesh: (4/xi) cos(theta) of a wall, the apparent angle read from
+// the first three interior cells with the side's own weights when the wall
+// has a hysteresis window (same rule as wet_factor).
+__device__ __forceinline__ double wet_factor_nu(const DevParams& P, int side, double C1, double C2, double C3)
+{
+    const double* ms = P.mside + side * MS_STRIDE;
+    const double s = C1 * (1.0 - C1);
+    if (!P.hyst[side] || !(s > 1e-3)) return ms[MS_WET];
+    const double dn = ms[MS_L0] * C1 + ms[MS_L0 + 1] * C2 + ms[MS_L0 + 2] * C3;
+    const double c = fmin(fmax(-dn / (ms[MS_K] * s), P.cos_adv[side]), P.cos_rec[side]);
+    return ms[MS_K] * c;
+}
+
 // Wall rule for ghost layer k (1..3) of `side` (0 x-, 1 x+, 2 y-, 3 y+):
 // m is the mirrored interior cell, Cw the C of the first interior cell, wet
-// the wall's wetting factor (wet_factor).
-template <typename R>
+// the wall's wetting factor (wet_factor; wet_factor_nu on a stretched mesh,
+// NU, where the ghost-to-mirror distance comes from the side's table).
+template <typename R, bool NU = false>
 __device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int k, const Cons<R>& m, double Cw,
                                               double wet)
 {
@@ -237,7 +271,10 @@ __device__ __forceinline__ Cons<R> wall_ghost(const DevParams& P, int side, int 
     const R gt = f == FLOW_NOSLIP ? -mt : mt;
     g.mx = xside ? gn : gt;
     g.my = xside ? gt : gn;
-    g.C = m.C + ((2 * k - 1) * wet) * Cw * (1.0 - Cw);
+    if (NU)
+        g.C = m.C + (P.mside[side * MS_STRIDE + MS_D + k - 1] * wet) * Cw * (1.0 - Cw);
+    else
+        g.C = m.C + ((2 * k - 1) * wet) * Cw * (1.0 - Cw);
     if (P.heat[side] == HEAT_DIRICHLET) {
         double Fl, Tm;
         closure(P, m.H, clamp01(m.C), Fl, Tm);
@@ -256,8 +293,8 @@ __device__ __forceinline__ int wrap(int i, int n)
 }
 
 // Conserved state at (i, j) for j inside [0, ny): interior read, periodic copy
-// or x-wall rule.
-template <typename R>
+// or x-wall rule (NU: stretched-mesh wall geometry).
+template <typename R, bool NU = false>
 __device__ __forceinline__ Cons<R> load_x(const DevParams& P, const State<R>& S, int i, int j)
 {
     if (i >= 0 && i < P.nx) return read_cell(S, P.pitch, i, j);
@@ -271,34 +308,45 @@ __device__ __forceinline__ Cons<R> load_x(const DevParams& P, const State<R>& S,
     const Cons<R> wm = read_cell(S, P.pitch, m, j);
     const size_t o = (size_t)j * P.pitch + first;
     const double Cw = S.C[o];
-    const double wet = P.hyst[side] ? wet_factor(P, side, Cw, S.C[o + in], S.C[o + 2 * in]) : P.wet[side];
-    return wall_ghost(P, side, k, wm, Cw, wet);
+    double wet;
+    if (NU)
+        wet = P.hyst[side] ? wet_factor_nu(P, side, Cw, S.C[o + in], S.C[o + 2 * in])
+                           : P.mside[side * MS_STRIDE + MS_WET];
+    else
+        wet = P.hyst[side] ? wet_factor(P, side, Cw, S.C[o + in], S.C[o + 2 * in]) : P.wet[side];
+    return wall_ghost<R, NU>(P, side, k, wm, Cw, wet);
 }
 
 // Conserved state at any (i, j) of the grid extended by the three-layer
 // ghost ring: x rule on the interior rows, then the y rule on every column
 // (corner cells take the y rule of x-ghost cells).  Indices beyond the ring
 // are clamped onto it (only partial edge tiles reach them; their results are
-// never stored).
-template <typename R>
+// never stored).  NU: stretched-mesh wall geometry.
+template <typename R, bool NU = false>
 __device__ __forceinline__ Cons<R> load_bc(const DevParams& P, const State<R>& S, int i, int j)
 {
     i = min(max(i, -NG), P.nx + NG - 1);
     j = min(max(j, -NG), P.ny + NG - 1);
-    if (j >= 0 && j < P.ny) return load_x(P, S, i, j);
-    if (P.periodic_y) return load_x(P, S, i, wrap(j, P.ny));
+    if (j >= 0 && j < P.ny) return load_x<R, NU>(P, S, i, j);
+    if (P.periodic_y) return load_x<R, NU>(P, S, i, wrap(j, P.ny));
     int side, k, m, first, in;
     if (j < 0) {
         side = 2; k = -j; m = k - 1; first = 0; in = 1;
     } else {
         side = 3; k = j - P.ny + 1; m = P.ny - k; first = P.ny - 1; in = -1;
     }
-    const Cons<R> wm = load_x(P, S, i, m);
-    const double Cw = load_x(P, S, i, first).C;
-    const double wet = P.hyst[side] ? wet_factor(P, side, Cw, load_x(P, S, i, first + in).C,
-                                                 load_x(P, S, i, first + 2 * in).C)
-                                    : P.wet[side];
-    return wall_ghost(P, side, k, wm, Cw, wet);
+    const Cons<R> wm = load_x<R, NU>(P, S, i, m);
+    const double Cw = load_x<R, NU>(P, S, i, first).C;
+    double wet;
+    if (NU)
+        wet = P.hyst[side] ? wet_factor_nu(P, side, Cw, load_x<R, NU>(P, S, i, first + in).C,
+                                           load_x<R, NU>(P, S, i, first + 2 * in).C)
+                           : P.mside[side * MS_STRIDE + MS_WET];
+    else
+        wet = P.hyst[side] ? wet_factor(P, side, Cw, load_x(P, S, i, first + in).C,
+                                        load_x(P, S, i, first + 2 * in).C)
+                           : P.wet[side];
+    return wall_ghost<R, NU>(P, side, k, wm, Cw, wet);
 }
 
 // Primitive record of one cell used by the face fluxes.
@@ -330,6 +378,18 @@ __device__ __forceinline__ double chem_potential(const DevParams& P, double C, d
                                                  double cS)
 {
     const double lap = (cE + cW + cN + cS - 4.0 * C) * P.inv_dx2;
+    return 2.0 * P.beta * C * (C - 1.0) * (2.0 * C - 1.0) - P.kappa * lap;
+}
+
+// The same on a stretched mesh: lap C from the second derivatives of the
+// parabolas through the cell (ghosted column li, row lj) and its neighbours.
+__device__ __forceinline__ double chem_potential_nu(const DevParams& P, int li, int lj, double C, double cE,
+                                                    double cW, double cN, double cS)
+{
+    const double* mx = P.mxc + li;
+    const double* my = P.myc + lj;
+    const double lap = mx[MESH_LM * P.msx] * cW + mx[MESH_L0 * P.msx] * C + mx[MESH_LP * P.msx] * cE +
+                       my[MESH_LM * P.msy] * cS + my[MESH_L0 * P.msy] * C + my[MESH_LP * P.msy] * cN;
     return 2.0 * P.beta * C * (C - 1.0) * (2.0 * C - 1.0) - P.kappa * lap;
 }
 
@@ -390,6 +450,28 @@ __device__ __forceinline__ void face_bases(const R* v, int a, int sn, int st, R 
     M = R(0.5) * ((va + c_h * ga) + (vb - c_h * gb));
     da = c_ds * (v[a + st] - v[a - st]);
     db = c_ds * (v[b + st] - v[b - st]);
+    dm = R(0.5) * (da + db);
+}
+
+// face_bases on a stretched mesh.  ca, cb: derivative weights (MESH_GM,
+// MESH_G0, MESH_GP) along n of cells a and b; ct: those along t of the row
+// (column) the face lies in; ha, hb: the two half widths along n; ds:
+// delta_t.  A, B, M and d have the meaning stated above, with the true
+// derivatives of the two cells.
+template <typename R>
+__device__ __forceinline__ void face_bases_nu(const R* v, int a, int sn, int st, const R ca[3], const R cb[3],
+                                              const R ct[3], R ha, R hb, R ds, R& A, R& B, R& M, R& da, R& db,
+                                              R& dm)
+{
+    const int b = a + sn;
+    const R va = v[a], vb = v[b];
+    const R ga = ca[0] * v[a - sn] + ca[1] * va + ca[2] * vb;
+    const R gb = cb[0] * va + cb[1] * vb + cb[2] * v[b + sn];
+    A = va + (ha - ds) * ga;
+    B = vb - (hb - ds) * gb;
+    M = R(0.5) * ((va + ha * ga) + (vb - hb * gb));
+    da = ds * (ct[0] * v[a - st] + ct[1] * va + ct[2] * v[a + st]);
+    db = ds * (ct[0] * v[b - st] + ct[1] * vb + ct[2] * v[b + st]);
     dm = R(0.5) * (da + db);
 }
 

@@ -10,7 +10,9 @@
 //   k_fill_ghosts / k_split_prims / k_split_faces / k_split_update
 //                   the same stage in four kernels with the intermediate
 //                   fields in HBM (ghosted state, primitive planes, face flux
-//                   planes); used for face-by-face checks and as a variant.
+//                   planes); used for face-by-face checks, as a variant,
+//                   and for stretched meshes (NU: per-column and per-row
+//                   geometry tables instead of one dx).
 //   k_init          primitive initial fields -> conserved vector.
 //   k_export        conserved or derived field -> dense double plane.
 //   k_reduce_*      FP64 integrals, deterministic two-pass wave reduction.
@@ -389,15 +391,16 @@ __global__ void __launch_bounds__(TX* TY)
 
 // ---------------------------------------------------------------------------
 // Split path.  Ghosted planes have (ny + 6) rows of gpitch elements; cell
-// (i, j) sits at (j + 3) * gpitch + i + 3.
+// (i, j) sits at (j + 3) * gpitch + i + 3.  NU: stretched mesh (the geometry
+// comes from the mesh tables of DevParams instead of dx).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, bool NU>
 __global__ void k_fill_ghosts(DevParams P, State<R> in, State<R> g, int gpitch)
 {
     const int li = blockIdx.x * blockDim.x + threadIdx.x;
     const int lj = blockIdx.y * blockDim.y + threadIdx.y;
     if (li >= P.nx + 2 * NG || lj >= P.ny + 2 * NG) return;
-    const Cons<R> w = load_bc(P, in, li - NG, lj - NG);
+    const Cons<R> w = load_bc<R, NU>(P, in, li - NG, lj - NG);
     const size_t q = (size_t)lj * gpitch + li;
     g.H[q] = w.H;
     g.p[q] = w.p;
@@ -406,7 +409,7 @@ __global__ void k_fill_ghosts(DevParams P, State<R> in, State<R> g, int gpitch)
     g.C[q] = w.C;
 }
 
-template <typename R>
+template <typename R, bool NU>
 __global__ void k_split_prims(DevParams P, State<R> g, int gpitch, R* prim, size_t pstride)
 {
     const int li = blockIdx.x * blockDim.x + threadIdx.x + 1;  // ring 2 of the ghosted grid
@@ -421,12 +424,24 @@ __global__ void k_split_prims(DevParams P, State<R> g, int gpitch, R* prim, size
     w.C = g.C[q];
     R pr[NPRIM + 1];
     primitives(P, w, pr);
-    pr[VMU] = R(chem_potential(P, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]));
+    if (NU)
+        pr[VMU] = R(chem_potential_nu(P, li, lj, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]));
+    else
+        pr[VMU] = R(chem_potential(P, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]));
 #pragma unroll
     for (int k = 0; k <= NPRIM; ++k) prim[k * pstride + q] = pr[k];
 }
 
-template <typename R, int LAT>
+// Derivative weights (MESH_GM, MESH_G0, MESH_GP) of ghosted index l.
+template <typename R>
+__device__ __forceinline__ void mesh_grad(const double* m, int stride, int l, R c[3])
+{
+    c[0] = R(m[MESH_GM * stride + l]);
+    c[1] = R(m[MESH_G0 * stride + l]);
+    c[2] = R(m[MESH_GP * stride + l]);
+}
+
+template <typename R, int LAT, bool NU>
 __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gpitch, R* Fx, R* Fy, int fpitch,
                               size_t fstride)
 {
@@ -434,14 +449,28 @@ __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gp
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const R i2dx = R(P.inv_2dx);
     const R c_sh = R(0.5 * P.dx - P.delta_t) * i2dx, c_h = R(0.5 * P.dx) * i2dx, c_ds = R(P.delta_t) * i2dx;
+    const R ds = R(P.delta_t);
     Bases<R> X;
     R F[5];
     if (i <= P.nx && j < P.ny) {  // x-face i between cells i-1 and i
         const int a = (j + NG) * gpitch + (i - 1 + NG);
+        R ca[3], cb[3], ct[3], ha = 0, hb = 0;
+        if (NU) {
+            mesh_grad(P.mxc, P.msx, i - 1 + NG, ca);
+            mesh_grad(P.mxc, P.msx, i + NG, cb);
+            mesh_grad(P.myc, P.msy, j + NG, ct);
+            ha = R(P.mxc[MESH_HW * P.msx + i - 1 + NG]);
+            hb = R(P.mxc[MESH_HW * P.msx + i + NG]);
+        }
 #pragma unroll
-        for (int k = 0; k < NPRIM; ++k)
-            face_bases(prim + k * pstride, a, 1, gpitch, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
-                       X.dm[k]);
+        for (int k = 0; k < NPRIM; ++k) {
+            if (NU)
+                face_bases_nu(prim + k * pstride, a, 1, gpitch, ca, cb, ct, ha, hb, ds, X.A[k], X.B[k], X.M[k],
+                              X.da[k], X.db[k], X.dm[k]);
+            else
+                face_bases(prim + k * pstride, a, 1, gpitch, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k],
+                           X.db[k], X.dm[k]);
+        }
         face_flux<R, LAT>(P, X, F);
         if (!P.periodic_x) {
             if (i == 0) wall_face(P, 0, F);
@@ -453,11 +482,23 @@ __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gp
     }
     if (i < P.nx && j <= P.ny) {  // y-face j between cells j-1 and j
         const int a = (j - 1 + NG) * gpitch + (i + NG);
+        R ca[3], cb[3], ct[3], ha = 0, hb = 0;
+        if (NU) {
+            mesh_grad(P.myc, P.msy, j - 1 + NG, ca);
+            mesh_grad(P.myc, P.msy, j + NG, cb);
+            mesh_grad(P.mxc, P.msx, i + NG, ct);
+            ha = R(P.myc[MESH_HW * P.msy + j - 1 + NG]);
+            hb = R(P.myc[MESH_HW * P.msy + j + NG]);
+        }
 #pragma unroll
         for (int k = 0; k < NPRIM; ++k) {
             const int ks = k == VU ? VV : (k == VV ? VU : k);
-            face_bases(prim + ks * pstride, a, gpitch, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
-                       X.dm[k]);
+            if (NU)
+                face_bases_nu(prim + ks * pstride, a, gpitch, 1, ca, cb, ct, ha, hb, ds, X.A[k], X.B[k], X.M[k],
+                              X.da[k], X.db[k], X.dm[k]);
+            else
+                face_bases(prim + ks * pstride, a, gpitch, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k],
+                           X.db[k], X.dm[k]);
         }
         face_flux<R, LAT>(P, X, F);
         if (!P.periodic_y) {
@@ -473,7 +514,7 @@ __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gp
     }
 }
 
-template <typename R>
+template <typename R, bool NU>
 __global__ void k_split_update(DevParams P, StageCoef K, const R* prim, size_t pstride, int gpitch, const R* Fx,
                                const R* Fy, int fpitch, size_t fstride, State<R> in, State<R> Wn, State<R> out,
                                R* fsdot, R* resid, size_t resid_stride)
@@ -481,13 +522,15 @@ __global__ void k_split_update(DevParams P, StageCoef K, const R* prim, size_t p
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= P.nx || j >= P.ny) return;
-    const R idx = R(1.0 / P.dx);
+    // Eq. (52) on a Cartesian cell: (1/V) S = 1/width along each direction
+    const R idx = NU ? R(P.mxc[MESH_IW * P.msx + i + NG]) : R(1.0 / P.dx);
+    const R idy = NU ? R(P.myc[MESH_IW * P.msy + j + NG]) : idx;
     const size_t o = (size_t)j * fpitch + i;
     R dF[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k)
         dF[k] = (Fx[k * fstride + o + 1] - Fx[k * fstride + o]) * idx +
-                (Fy[k * fstride + o + fpitch] - Fy[k * fstride + o]) * idx;
+                (Fy[k * fstride + o + fpitch] - Fy[k * fstride + o]) * idy;
     const size_t c2 = (size_t)(j + NG) * gpitch + i + NG;
     R c[NPRIM + 1];
 #pragma unroll
@@ -497,12 +540,27 @@ __global__ void k_split_update(DevParams P, StageCoef K, const R* prim, size_t p
     const R* pv = prim + VV * pstride;
     const R* pr = prim + NPRIM * pstride;
     const R* pm = prim + VMU * pstride;
-    const R dudx = (pu[c2 + 1] - pu[c2 - 1]) * i2dx;
-    const R dvdy = (pv[c2 + gpitch] - pv[c2 - gpitch]) * i2dx;
-    const R drx = (pr[c2 + 1] - pr[c2 - 1]) * i2dx;
-    const R dry = (pr[c2 + gpitch] - pr[c2 - gpitch]) * i2dx;
-    const R dmx = (pm[c2 + 1] - pm[c2 - 1]) * i2dx;
-    const R dmy = (pm[c2 + gpitch] - pm[c2 - gpitch]) * i2dx;
+    R dudx, dvdy, drx, dry, dmx, dmy;
+    if (NU) {
+        R gx[3], gy[3];
+        mesh_grad(P.mxc, P.msx, i + NG, gx);
+        mesh_grad(P.myc, P.msy, j + NG, gy);
+        auto ddx = [&](const R* v) { return gx[0] * v[c2 - 1] + gx[1] * v[c2] + gx[2] * v[c2 + 1]; };
+        auto ddy = [&](const R* v) { return gy[0] * v[c2 - gpitch] + gy[1] * v[c2] + gy[2] * v[c2 + gpitch]; };
+        dudx = ddx(pu);
+        dvdy = ddy(pv);
+        drx = ddx(pr);
+        dry = ddy(pr);
+        dmx = ddx(pm);
+        dmy = ddy(pm);
+    } else {
+        dudx = (pu[c2 + 1] - pu[c2 - 1]) * i2dx;
+        dvdy = (pv[c2 + gpitch] - pv[c2 - gpitch]) * i2dx;
+        drx = (pr[c2 + 1] - pr[c2 - 1]) * i2dx;
+        dry = (pr[c2 + gpitch] - pr[c2 - gpitch]) * i2dx;
+        dmx = (pm[c2 + 1] - pm[c2 - 1]) * i2dx;
+        dmy = (pm[c2 + gpitch] - pm[c2 - gpitch]) * i2dx;
+    }
     const size_t q = (size_t)j * P.pitch + i;
     const Cons<R> wk = read_cell(in, P.pitch, i, j);
     const Cons<R> wnk = read_at(Wn, q);
@@ -576,9 +634,15 @@ __global__ void k_export(DevParams P, State<R> S, const R* fsdot, int what, doub
             default: x = fsdot[q]; break;
         }
     } else if (what == 12) {
-        const double cE = load_bc(P, S, i + 1, j).C, cW = load_bc(P, S, i - 1, j).C;
-        const double cN = load_bc(P, S, i, j + 1).C, cS = load_bc(P, S, i, j - 1).C;
-        x = chem_potential(P, w.C, cE, cW, cN, cS);
+        if (P.mside) {
+            const double cE = load_bc<R, true>(P, S, i + 1, j).C, cW = load_bc<R, true>(P, S, i - 1, j).C;
+            const double cN = load_bc<R, true>(P, S, i, j + 1).C, cS = load_bc<R, true>(P, S, i, j - 1).C;
+            x = chem_potential_nu(P, i + NG, j + NG, w.C, cE, cW, cN, cS);
+        } else {
+            const double cE = load_bc(P, S, i + 1, j).C, cW = load_bc(P, S, i - 1, j).C;
+            const double cN = load_bc(P, S, i, j + 1).C, cS = load_bc(P, S, i, j - 1).C;
+            x = chem_potential(P, w.C, cE, cW, cN, cS);
+        }
     } else {
         const double Cc = clamp01(w.C);
         double Fl, T;
@@ -603,7 +667,7 @@ __global__ void k_export_ghosted(DevParams P, State<R> S, double* dst, int gnx, 
     const int li = blockIdx.x * blockDim.x + threadIdx.x;
     const int lj = blockIdx.y * blockDim.y + threadIdx.y;
     if (li >= gnx || lj >= gny) return;
-    const Cons<R> w = load_bc(P, S, li - NG, lj - NG);
+    const Cons<R> w = P.mside ? load_bc<R, true>(P, S, li - NG, lj - NG) : load_bc(P, S, li - NG, lj - NG);
     const size_t n = (size_t)gnx * gny, s = (size_t)lj * gnx + li;
     dst[s] = w.H;
     dst[n + s] = w.p;
@@ -648,15 +712,18 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(DevParams P, Sta
         const double Fs = Cc * (1.0 - Fl);
         const double rho = mix<double>(P.rho, Cc, Fs);
         const double u = 3.0 * (double)w.mx / rho, v = 3.0 * (double)w.my / rho;
-        acc[0] += rho;
-        acc[1] += w.C;
-        acc[2] += w.H;
-        acc[3] += Fs;
+        // stretched mesh: cell volume and height inside the sums (uniform: dx^2 and dx after them)
+        const double hy = P.mside ? 2.0 * P.myc[MESH_HW * P.msy + j + NG] : 1.0;
+        const double dV = P.mside ? 2.0 * P.mxc[MESH_HW * P.msx + i + NG] * hy : 1.0;
+        acc[0] += rho * dV;
+        acc[1] += w.C * dV;
+        acc[2] += w.H * dV;
+        acc[3] += Fs * dV;
         acc[4] = fmax(acc[4], sqrt(u * u + v * v));
         const bool finite = isfinite(w.H) && isfinite((double)w.p) && isfinite((double)w.mx) &&
                             isfinite((double)w.my) && isfinite(w.C);
         acc[5] += finite ? 0.0 : 1.0;
-        if (i == ic) acc[6] += Fs;
+        if (i == ic) acc[6] += Fs * hy;
     }
     const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
 #pragma unroll
@@ -781,25 +848,35 @@ hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, 
     return hipGetLastError();
 }
 
+template <typename R, bool NU>
+hipError_t split_stages(const DevParams& P, const SplitScratch<R>& X, const StageCoef& K, const State<R>& in,
+                        const State<R>& Wn, const State<R>& out, R* fsdot, R* resid, size_t resid_stride,
+                        hipStream_t st)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL((k_fill_ghosts<R, NU>), grid2(P.nx + 2 * NG, P.ny + 2 * NG, b), b, 0, st, P, in, X.g,
+                       X.gpitch);
+    hipLaunchKernelGGL((k_split_prims<R, NU>), grid2(P.nx + 4, P.ny + 4, b), b, 0, st, P, X.g, X.gpitch, X.prim,
+                       X.pstride);
+    if (P.lattice_hg == 5)
+        hipLaunchKernelGGL((k_split_faces<R, 5, NU>), grid2(P.nx + 1, P.ny + 1, b), b, 0, st, P, (const R*)X.prim,
+                           X.pstride, X.gpitch, X.Fx, X.Fy, X.fpitch, X.fstride);
+    else
+        hipLaunchKernelGGL((k_split_faces<R, 9, NU>), grid2(P.nx + 1, P.ny + 1, b), b, 0, st, P, (const R*)X.prim,
+                           X.pstride, X.gpitch, X.Fx, X.Fy, X.fpitch, X.fstride);
+    hipLaunchKernelGGL((k_split_update<R, NU>), grid2(P.nx, P.ny, b), b, 0, st, P, K, (const R*)X.prim, X.pstride,
+                       X.gpitch, (const R*)X.Fx, (const R*)X.Fy, X.fpitch, X.fstride, in, Wn, out, fsdot, resid,
+                       resid_stride);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_stage_split(const DevParams& P, const SplitScratch<R>& X, const StageCoef& K, const State<R>& in,
                               const State<R>& Wn, const State<R>& out, R* fsdot, R* resid, size_t resid_stride,
                               hipStream_t st)
 {
-    const dim3 b(64, 4);
-    hipLaunchKernelGGL(k_fill_ghosts<R>, grid2(P.nx + 2 * NG, P.ny + 2 * NG, b), b, 0, st, P, in, X.g, X.gpitch);
-    hipLaunchKernelGGL(k_split_prims<R>, grid2(P.nx + 4, P.ny + 4, b), b, 0, st, P, X.g, X.gpitch, X.prim,
-                       X.pstride);
-    if (P.lattice_hg == 5)
-        hipLaunchKernelGGL((k_split_faces<R, 5>), grid2(P.nx + 1, P.ny + 1, b), b, 0, st, P, (const R*)X.prim,
-                           X.pstride, X.gpitch, X.Fx, X.Fy, X.fpitch, X.fstride);
-    else
-        hipLaunchKernelGGL((k_split_faces<R, 9>), grid2(P.nx + 1, P.ny + 1, b), b, 0, st, P, (const R*)X.prim,
-                           X.pstride, X.gpitch, X.Fx, X.Fy, X.fpitch, X.fstride);
-    hipLaunchKernelGGL(k_split_update<R>, grid2(P.nx, P.ny, b), b, 0, st, P, K, (const R*)X.prim, X.pstride,
-                       X.gpitch, (const R*)X.Fx, (const R*)X.Fy, X.fpitch, X.fstride, in, Wn, out, fsdot, resid,
-                       resid_stride);
-    return hipGetLastError();
+    if (P.mside) return split_stages<R, true>(P, X, K, in, Wn, out, fsdot, resid, resid_stride, st);
+    return split_stages<R, false>(P, X, K, in, Wn, out, fsdot, resid, resid_stride, st);
 }
 
 template <typename R>

@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, 
 FP64, FP32 = 0, 1
 KERNEL_FUSED, KERNEL_SPLIT, KERNEL_AUTO = 0, 1, 2
 INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
              W_GHOSTED=14)
 SCALAR_DIAG = 100
@@ -50,7 +50,8 @@ class eulbfs_params(ct.Structure):
         ("sigma", ct.c_double), ("xi", ct.c_double), ("mobility", ct.c_double), ("Qg", ct.c_double),
         ("gx", ct.c_double), ("gy", ct.c_double),
         ("bc", eulbfs_bc * 4),
-        ("tile_x", ct.c_int32), ("tile_y", ct.c_int32), ("reserved", ct.c_int32 * 6),
+        ("tile_x", ct.c_int32), ("tile_y", ct.c_int32),
+        ("x_width", ct.POINTER(ct.c_double)), ("y_width", ct.POINTER(ct.c_double)), ("reserved", ct.c_int32 * 2),
     ]
 
 
@@ -127,6 +128,15 @@ def params_from_problem(pr, precision: int = None, kernel: int = KERNEL_FUSED, t
             P.bc[k].T_w, P.bc[k].theta_deg = w.T_w, w.theta_deg
             P.bc[k].theta_adv, P.bc[k].theta_rec = w.theta_adv, w.theta_rec
     P.tile_x, P.tile_y = tile
+    # stretched mesh: host arrays, kept alive by the struct (the library copies them at create)
+    P._widths = []
+    for name, src, n in (("x_width", pr.x_width, pr.nx), ("y_width", pr.y_width, pr.ny)):
+        if src is not None:
+            a = np.ascontiguousarray(src, dtype=np.float64)
+            if a.shape != (n,):
+                raise ValueError(f"{name}: expected {n} widths, got shape {a.shape}")
+            P._widths.append(a)
+            setattr(P, name, a.ctypes.data_as(ct.POINTER(ct.c_double)))
     return P
 
 

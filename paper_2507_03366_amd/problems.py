@@ -158,7 +158,9 @@ def seeded_fields(pr: Problem, seed: int, amp: float = 1.0) -> InitialState:
     """Smooth random primitive fields for parity checks (not a physical state)."""
     rng = np.random.default_rng(seed)
     X, Y = cell_centres(pr)
-    Lx, Ly = pr.nx * pr.dx, pr.ny * pr.dx
+    wx, wy = widths(pr)
+    Lx = pr.nx * pr.dx if pr.x_width is None else float(wx.sum())
+    Ly = pr.ny * pr.dx if pr.y_width is None else float(wy.sum())
 
     def smooth(a0, a1):
         out = np.full(X.shape, a0)

@@ -32,11 +32,13 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout_matches_header():
-    # 8 + 6*4 ints, 3 + 12 + 9 doubles, 4 bc of 48 bytes, 8 ints (the library
-    # itself rejects a struct_size other than its sizeof(eulbfs_params))
+    # 8 + 6*4 ints, 3 + 12 + 9 doubles, 4 bc of 48 bytes, 2 ints, 2 pointers,
+    # 2 ints (the library itself rejects a struct_size other than its
+    # sizeof(eulbfs_params))
     assert ct.sizeof(E.eulbfs_bc) == 48
-    assert ct.sizeof(E.eulbfs_params) == 32 + 24 * 8 + 4 * 48 + 8 * 4
+    assert ct.sizeof(E.eulbfs_params) == 32 + 24 * 8 + 4 * 48 + 2 * 4 + 2 * 8 + 2 * 4
     assert E.eulbfs_params.dx.offset == 32
+    assert E.eulbfs_params.x_width.offset == 32 + 24 * 8 + 4 * 48 + 2 * 4
 
 
 def _params(**kw):
@@ -123,3 +125,27 @@ def test_create_rejects_before_touching_the_device():
     with pytest.raises(E.EulbfsError) as ei:
         E.eulbfs_create(P, __import__("numpy").zeros(6 * 64 * 64))
     assert ei.value.code == E.EINVAL
+
+
+def test_stretched_mesh_parameters():
+    """Widths must be finite and > 0; delta_t is bounded by half the smallest
+    width; the split kernels' workspace (with the mesh tables) is sized for
+    AUTO; the batch API sizes nothing for a stretched mesh."""
+    import numpy as np
+
+    pr, _ = PB.static_droplet(n=64, R=16)
+    w = np.linspace(0.6, 1.4, 64)
+    P = E.params_from_problem(pr.replace(x_width=w, delta_t=0.3), kernel=E.KERNEL_AUTO)
+    assert E.eulbfs_check_params(P) == ""
+    uni = E.eulbfs_workspace_bytes(E.params_from_problem(pr.replace(delta_t=0.3), kernel=E.KERNEL_SPLIT))
+    assert E.eulbfs_workspace_bytes(P) > uni
+    assert E.eulbfs_batch_request_bytes(P) == 0
+    P = E.params_from_problem(pr.replace(y_width=w, delta_t=0.31), kernel=E.KERNEL_SPLIT)
+    assert "delta_t" in E.eulbfs_check_params(P)
+    bad = w.copy()
+    bad[5] = 0.0
+    P = E.params_from_problem(pr.replace(x_width=bad, delta_t=0.1), kernel=E.KERNEL_SPLIT)
+    assert "widths" in E.eulbfs_check_params(P)
+    bad[5] = np.nan
+    P = E.params_from_problem(pr.replace(y_width=bad, delta_t=0.1), kernel=E.KERNEL_SPLIT)
+    assert "widths" in E.eulbfs_check_params(P)
