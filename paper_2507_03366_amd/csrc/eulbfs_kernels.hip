@@ -441,8 +441,13 @@ __device__ __forceinline__ void mesh_grad(const double* m, int stride, int l, R 
     c[2] = R(m[MESH_GP * stride + l]);
 }
 
+// The split kernels launch 64x4 threads; the bound lets the face and update
+// kernels keep their bases and coefficients in registers (the default bound of
+// 1024 threads caps a wave at 128 VGPRs, and the stretched-mesh variants spilled).
+constexpr int SPLIT_THREADS = 256;
+
 template <typename R, int LAT, bool NU>
-__global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gpitch, R* Fx, R* Fy, int fpitch,
+__global__ void __launch_bounds__(SPLIT_THREADS) k_split_faces(DevParams P, const R* prim, size_t pstride, int gpitch, R* Fx, R* Fy, int fpitch,
                               size_t fstride)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -515,7 +520,7 @@ __global__ void k_split_faces(DevParams P, const R* prim, size_t pstride, int gp
 }
 
 template <typename R, bool NU>
-__global__ void k_split_update(DevParams P, StageCoef K, const R* prim, size_t pstride, int gpitch, const R* Fx,
+__global__ void __launch_bounds__(SPLIT_THREADS) k_split_update(DevParams P, StageCoef K, const R* prim, size_t pstride, int gpitch, const R* Fx,
                                const R* Fy, int fpitch, size_t fstride, State<R> in, State<R> Wn, State<R> out,
                                R* fsdot, R* resid, size_t resid_stride)
 {
@@ -853,7 +858,7 @@ hipError_t split_stages(const DevParams& P, const SplitScratch<R>& X, const Stag
                         const State<R>& Wn, const State<R>& out, R* fsdot, R* resid, size_t resid_stride,
                         hipStream_t st)
 {
-    const dim3 b(64, 4);
+    const dim3 b(64, SPLIT_THREADS / 64);
     hipLaunchKernelGGL((k_fill_ghosts<R, NU>), grid2(P.nx + 2 * NG, P.ny + 2 * NG, b), b, 0, st, P, in, X.g,
                        X.gpitch);
     hipLaunchKernelGGL((k_split_prims<R, NU>), grid2(P.nx + 4, P.ny + 4, b), b, 0, st, P, X.g, X.gpitch, X.prim,
