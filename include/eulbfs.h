@@ -69,7 +69,7 @@ extern "C" {
 #define EULBFS_KERNEL_AUTO 2  /* FUSED with the tile shape that create timed
                                  fastest on the initial state (cached per
                                  process for the grid, precision and lattice);
-                                 SPLIT on a stretched mesh */
+                                 FUSED 32x16 on a stretched mesh */
 
 /* One side of the domain.  Sides are indexed 0: x-, 1: x+, 2: y-, 3: y+.
  * periodic must agree on opposite sides.  For a wall:
@@ -157,10 +157,11 @@ typedef struct {
  * the distance between them in place of (2k - 1) dx, and the hysteresis
  * angle reads dC/dn from the parabola through the first three cell centres.
  * Widths must be finite and > 0; both arrays are copied by eulbfs_create and
- * may be freed afterwards.  Such a mesh runs on the split kernels: kernel
- * AUTO selects them, FUSED returns EULBFS_ENOTSUP, and the batch API refuses
- * it (EULBFS_ENOTSUP; eulbfs_batch_request_bytes returns 0).  Diagnostic
- * integrals weight each cell by w_i h_j and the tip height by h_j. */
+ * may be freed afterwards.  FUSED and AUTO run such a mesh on the fused kernel
+ * with 32x16 tiles (tile_x and tile_y are ignored, nothing is autotuned),
+ * SPLIT on the split kernels; the batch API refuses it (EULBFS_ENOTSUP;
+ * eulbfs_batch_request_bytes returns 0).  Diagnostic integrals weight each
+ * cell by w_i h_j and the tip height by h_j. */
 
 /* Initial state. */
 #define EULBFS_INIT_PRIMITIVE 0 /* 6 planes: T, F_l, C, u, v, p                */

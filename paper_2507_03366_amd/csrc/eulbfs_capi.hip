@@ -163,7 +163,7 @@ DevParams make_dev(const eulbfs_params* p)
     d.gy = p->gy;
     d.expansion = 1.0 - p->rho[0] / p->rho[1];
     // compile-time fast paths valid for these constants (same quantities up to rounding)
-    d.fast = (0.5 * p->dx - p->delta_t == 0.0 ? FAST_HALF : 0) |
+    d.fast = (0.5 * p->dx - p->delta_t == 0.0 && !stretched(p) ? FAST_HALF : 0) |
              (p->cp[0] == p->cp[1] && p->cp[1] == p->cp[2] ? FAST_UCP : 0);
     d.Hs_u = p->cp[0] * p->T_s;
     d.Hl_u = p->cp[0] * p->T_l + p->latent;
@@ -215,8 +215,7 @@ Layout make_layout(const eulbfs_params* p)
     off += align_up((size_t)L.red_blocks * NRED * 8);
     L.red_out = off;
     off += align_up(16 * 8);
-    // a stretched mesh runs on the split kernels (AUTO picks them; FUSED is refused at create)
-    L.split = p->kernel == EULBFS_KERNEL_SPLIT || (stretched(p) && p->kernel == EULBFS_KERNEL_AUTO);
+    L.split = p->kernel == EULBFS_KERNEL_SPLIT;
     L.gpitch = round_pitch(p->nx + 2 * NG);
     L.fpitch = round_pitch(p->nx + 1);
     L.gplane_H = align_up((size_t)(p->ny + 2 * NG) * L.gpitch * 8);  // H and C planes
@@ -690,11 +689,16 @@ int autotune(eulbfs_solver* h, const eulbfs_init* init)
 template <typename R>
 int setup_schedule(eulbfs_solver* h, const eulbfs_init* init)
 {
-    if (h->L.split) {  // SPLIT, or a stretched mesh
+    if (h->L.split) {
         h->sched = EULBFS_KERNEL_SPLIT;
         return EULBFS_OK;
     }
     h->sched = EULBFS_KERNEL_FUSED;
+    if (h->dp.mside) {  // a stretched mesh has one fused tile shape
+        static_assert(NU_TX == 32 && NU_TY == 16, "the stretched-mesh tile is reported as TILE_32x16");
+        h->tile = TILE_32x16;
+        return EULBFS_OK;
+    }
     if (h->prm.kernel == EULBFS_KERNEL_AUTO) return autotune<R>(h, init);
     return EULBFS_OK;
 }
@@ -740,8 +744,6 @@ int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
     if (!init || !init->planes) return set_err(err, EULBFS_EINVAL, "init or init->planes is NULL");
     if (init->kind != EULBFS_INIT_PRIMITIVE && init->kind != EULBFS_INIT_CONSERVED)
         return set_err(err, EULBFS_EINVAL, "unknown init kind");
-    if (stretched(prm) && prm->kernel == EULBFS_KERNEL_FUSED)
-        return set_err(err, EULBFS_ENOTSUP, "stretched meshes run on the split kernels (kernel SPLIT or AUTO)");
     const Layout L = make_layout(prm);
     if (d_ws && ws_bytes < L.total) return set_err(err, EULBFS_ENOMEM, "workspace smaller than eulbfs_workspace_bytes()");
     if (d_ws && ((uintptr_t)d_ws % ALIGN) != 0) return set_err(err, EULBFS_EINVAL, "workspace must be 256-byte aligned");

@@ -35,6 +35,11 @@ constexpr int NXCD = 8;  // accelerator complex dies of an MI355X, each with its
 // solves/s).
 constexpr int BATCH_TX = 32, BATCH_TY = 16;
 
+// Tile of the fused stage kernel on a stretched mesh (one shape is compiled:
+// its face loop holds the mesh weights beside the bases, which a 1024-thread
+// tile could not keep within its 128 VGPRs).
+constexpr int NU_TX = 32, NU_TY = 16;
+
 // One request of a batch: its constants, its three copies of W (W^n, W1, W2)
 // and its dF_s/dt plane, and where its tiles start in the batch's tile list.
 template <typename R>

@@ -105,9 +105,22 @@ __device__ __forceinline__ R plane_rho(const DevParams& P, const R (*sP)[N], int
     else return mix<R>(P.rho, clamp01(sP[VC][q]), sP[VFS][q]);
 }
 
+// Derivative weights (MESH_GM, MESH_G0, MESH_GP) of ghosted index l.
+template <typename R>
+__device__ __forceinline__ void mesh_grad(const double* m, int stride, int l, R c[3])
+{
+    c[0] = R(m[MESH_GM * stride + l]);
+    c[1] = R(m[MESH_G0 * stride + l]);
+    c[2] = R(m[MESH_GP * stride + l]);
+}
+
 // One tile of one stage: cells [i0, i0+TX) x [j0, j0+TY) of the grid described
-// by P.  Every thread of the workgroup must call it (it synchronises).
-template <typename R, int LAT, int FAST, int TX, int TY>
+// by P.  Every thread of the workgroup must call it (it synchronises).  NU:
+// stretched mesh, the geometry read from the mesh tables of P (ghosted column
+// and row indices clamped to the table's valid range; only cells beyond the
+// ghost ring of a partial tile are clamped, and their results are never
+// stored).
+template <typename R, int LAT, int FAST, int TX, int TY, bool NU = false>
 __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& K, const State<R>& in,
                                            const State<R>& Wn, const State<R>& out, R* fsdot, int i0, int j0)
 {
@@ -189,9 +202,14 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             const int m = lo ? k - 1 : n - k, first = lo ? 0 : n - 1, dir = lo ? 1 : -1;
             const int qm = base + m * stride, qf = base + first * stride;
             const double Cw = sC[qf];
-            const double wet = P.hyst[side] ? wet_factor(P, side, Cw, sC[qf + dir * stride], sC[qf + 2 * dir * stride])
-                                            : P.wet[side];
-            return wall_ghost(P, side, k, cons_at(qm), Cw, wet);
+            double wet;
+            if (NU)
+                wet = P.hyst[side] ? wet_factor_nu(P, side, Cw, sC[qf + dir * stride], sC[qf + 2 * dir * stride])
+                                   : P.mside[side * MS_STRIDE + MS_WET];
+            else
+                wet = P.hyst[side] ? wet_factor(P, side, Cw, sC[qf + dir * stride], sC[qf + 2 * dir * stride])
+                                   : P.wet[side];
+            return wall_ghost<R, NU>(P, side, k, cons_at(qm), Cw, wet);
         };
         __syncthreads();
         // One thread per ghost cell, the ghost columns (rows) of one side at a
@@ -227,6 +245,11 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     }
     __syncthreads();
 
+    // ghosted column / row index of the tile + 2 layers (li, lj in [0, W2)),
+    // clamped to the rows of the tables that hold derivative weights
+    auto gcol = [&](int li) { return min(i0 + li + 1, P.nx + 2 * NG - 2); };
+    auto grow = [&](int lj) { return min(j0 + lj + 1, P.ny + 2 * NG - 2); };
+
     // 2. primitives and mu_c on the tile and two halo layers
     for (int q = tid; q < W2 * H2; q += NT) {
         const int li = q % W2, lj = q / W2;
@@ -239,7 +262,11 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
         w.C = sC[q3];
         R pr[NPRIM + 1];
         primitives<R, FAST>(P, w, pr);
-        pr[VMU] = R(chem_potential(P, w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3], sC[q3 - W3]));
+        if (NU)
+            pr[VMU] = R(chem_potential_nu(P, gcol(li), grow(lj), w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3],
+                                          sC[q3 - W3]));
+        else
+            pr[VMU] = R(chem_potential(P, w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3], sC[q3 - W3]));
 #pragma unroll
         for (int k = 0; k < L::NPL; ++k) sP[k][q] = pr[k];
     }
@@ -250,6 +277,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     // takes either the x or the y branch in a pass, never both.
     const R i2dx = R(P.inv_2dx);
     const R c_sh = R(0.5 * P.dx - P.delta_t) * i2dx, c_h = R(0.5 * P.dx) * i2dx, c_ds = R(P.delta_t) * i2dx;
+    const R ds = R(P.delta_t);
     constexpr int NF = NFX + NFY;
     constexpr int NFXP = (NFX + 63) / 64 * 64;
     static_assert(NT % 64 == 0, "whole waves per workgroup");
@@ -274,10 +302,23 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
         if (f < NFX) {
             const int fi = f % (TX + 1), fj = f / (TX + 1);
             const int a = (fj + 2) * W2 + fi + 1;
+            if (NU) {
+                R ca[3], cb[3], ct[3];
+                const int la = gcol(fi + 1), lb = gcol(fi + 2);
+                mesh_grad(P.mxc, P.msx, la, ca);
+                mesh_grad(P.mxc, P.msx, lb, cb);
+                mesh_grad(P.myc, P.msy, grow(fj + 2), ct);
+                const R ha = R(P.mxc[MESH_HW * P.msx + la]), hb = R(P.mxc[MESH_HW * P.msx + lb]);
 #pragma unroll
-            for (int k = 0; k < NPRIM; ++k)
-                face_bases<R, FAST>(sP[k], a, 1, W2, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
-                                    X.dm[k]);
+                for (int k = 0; k < NPRIM; ++k)
+                    face_bases_nu(sP[k], a, 1, W2, ca, cb, ct, ha, hb, ds, X.A[k], X.B[k], X.M[k], X.da[k],
+                                  X.db[k], X.dm[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NPRIM; ++k)
+                    face_bases<R, FAST>(sP[k], a, 1, W2, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k],
+                                        X.db[k], X.dm[k]);
+            }
             X.rho_a = plane_rho<R, RHO>(P, sP, a);
             X.rho_b = plane_rho<R, RHO>(P, sP, a + 1);
             face_flux<R, LAT, FAST>(P, X, F);
@@ -292,11 +333,26 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             const int g = f - NFX;
             const int fi = g % TX, fj = g / TX;
             const int a = (fj + 1) * W2 + fi + 2;
+            if (NU) {
+                R ca[3], cb[3], ct[3];
+                const int la = grow(fj + 1), lb = grow(fj + 2);
+                mesh_grad(P.myc, P.msy, la, ca);
+                mesh_grad(P.myc, P.msy, lb, cb);
+                mesh_grad(P.mxc, P.msx, gcol(fi + 2), ct);
+                const R ha = R(P.myc[MESH_HW * P.msy + la]), hb = R(P.myc[MESH_HW * P.msy + lb]);
 #pragma unroll
-            for (int k = 0; k < NPRIM; ++k) {
-                const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
-                face_bases<R, FAST>(sP[ks], a, W2, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k], X.db[k],
-                                    X.dm[k]);
+                for (int k = 0; k < NPRIM; ++k) {
+                    const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
+                    face_bases_nu(sP[ks], a, W2, 1, ca, cb, ct, ha, hb, ds, X.A[k], X.B[k], X.M[k], X.da[k],
+                                  X.db[k], X.dm[k]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NPRIM; ++k) {
+                    const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
+                    face_bases<R, FAST>(sP[ks], a, W2, 1, c_sh, c_h, c_ds, X.A[k], X.B[k], X.M[k], X.da[k],
+                                        X.db[k], X.dm[k]);
+                }
             }
             X.rho_a = plane_rho<R, RHO>(P, sP, a);
             X.rho_b = plane_rho<R, RHO>(P, sP, a + W2);
@@ -332,22 +388,38 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     if (!own) return;  // no barrier follows in this tile
     const int fl = ty * (TX + 1) + tx;
     const int fb = NFX + ty * TX + tx;
-    const R idx = R(1.0 / P.dx);
+    // Eq. (52) on a Cartesian cell: (1/V) S = 1/width along each direction
+    const R idx = NU ? R(P.mxc[MESH_IW * P.msx + i + NG]) : R(1.0 / P.dx);
+    const R idy = NU ? R(P.myc[MESH_IW * P.msy + j + NG]) : idx;
     R dF[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k)
-        dF[k] = (sF[k * NF + fl + 1] - sF[k * NF + fl]) * idx + (sF[k * NF + fb + TX] - sF[k * NF + fb]) * idx;
+        dF[k] = (sF[k * NF + fl + 1] - sF[k * NF + fl]) * idx + (sF[k * NF + fb + TX] - sF[k * NF + fb]) * idy;
     const int c2 = (ty + 2) * W2 + tx + 2;
     R c[NPRIM + 1];
 #pragma unroll
     for (int k = 0; k < NPRIM; ++k) c[k] = sP[k][c2];
     c[NPRIM] = plane_rho<R, RHO>(P, sP, c2);
-    const R dudx = (sP[VU][c2 + 1] - sP[VU][c2 - 1]) * i2dx;
-    const R dvdy = (sP[VV][c2 + W2] - sP[VV][c2 - W2]) * i2dx;
-    const R drx = (plane_rho<R, RHO>(P, sP, c2 + 1) - plane_rho<R, RHO>(P, sP, c2 - 1)) * i2dx;
-    const R dry = (plane_rho<R, RHO>(P, sP, c2 + W2) - plane_rho<R, RHO>(P, sP, c2 - W2)) * i2dx;
-    const R dmx = (sP[VMU][c2 + 1] - sP[VMU][c2 - 1]) * i2dx;
-    const R dmy = (sP[VMU][c2 + W2] - sP[VMU][c2 - W2]) * i2dx;
+    R dudx, dvdy, drx, dry, dmx, dmy;
+    if (NU) {
+        R gx[3], gy[3];
+        mesh_grad(P.mxc, P.msx, i + NG, gx);
+        mesh_grad(P.myc, P.msy, j + NG, gy);
+        dudx = gx[0] * sP[VU][c2 - 1] + gx[1] * sP[VU][c2] + gx[2] * sP[VU][c2 + 1];
+        dvdy = gy[0] * sP[VV][c2 - W2] + gy[1] * sP[VV][c2] + gy[2] * sP[VV][c2 + W2];
+        drx = gx[0] * plane_rho<R, RHO>(P, sP, c2 - 1) + gx[1] * c[NPRIM] + gx[2] * plane_rho<R, RHO>(P, sP, c2 + 1);
+        dry = gy[0] * plane_rho<R, RHO>(P, sP, c2 - W2) + gy[1] * c[NPRIM] +
+              gy[2] * plane_rho<R, RHO>(P, sP, c2 + W2);
+        dmx = gx[0] * sP[VMU][c2 - 1] + gx[1] * sP[VMU][c2] + gx[2] * sP[VMU][c2 + 1];
+        dmy = gy[0] * sP[VMU][c2 - W2] + gy[1] * sP[VMU][c2] + gy[2] * sP[VMU][c2 + W2];
+    } else {
+        dudx = (sP[VU][c2 + 1] - sP[VU][c2 - 1]) * i2dx;
+        dvdy = (sP[VV][c2 + W2] - sP[VV][c2 - W2]) * i2dx;
+        drx = (plane_rho<R, RHO>(P, sP, c2 + 1) - plane_rho<R, RHO>(P, sP, c2 - 1)) * i2dx;
+        dry = (plane_rho<R, RHO>(P, sP, c2 + W2) - plane_rho<R, RHO>(P, sP, c2 - W2)) * i2dx;
+        dmx = (sP[VMU][c2 + 1] - sP[VMU][c2 - 1]) * i2dx;
+        dmy = (sP[VMU][c2 + W2] - sP[VMU][c2 - W2]) * i2dx;
+    }
     cell_update<R, FAST>(P, K, c, wk, wnk, fsd, dudx, dvdy, drx, dry, dmx, dmy, dF, out, fsdot, (R*)nullptr, 0, q);
 }
 
@@ -355,7 +427,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
 // eight XCDs of the chip, each with its own L2; giving every XCD a
 // contiguous run of tiles keeps the halo rows a tile shares with its
 // neighbours in the same L2.
-template <typename R, int LAT, int FAST, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY, bool NU = false>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_fused(DevParams P, StageCoef K, State<R> in, State<R> Wn, State<R> out, R* fsdot, int tiles_x,
                   int ntiles, int per_xcd)
@@ -363,7 +435,7 @@ __global__ void __launch_bounds__(TX* TY)
     const int b = blockIdx.x;
     const int t = (b % NXCD) * per_xcd + b / NXCD;
     if (t >= ntiles) return;
-    stage_tile<R, LAT, FAST, TX, TY>(P, K, in, Wn, out, fsdot, (t % tiles_x) * TX, (t / tiles_x) * TY);
+    stage_tile<R, LAT, FAST, TX, TY, NU>(P, K, in, Wn, out, fsdot, (t % tiles_x) * TX, (t / tiles_x) * TY);
 }
 
 // One stage of every grid of a batch: one workgroup per tile of the
@@ -430,15 +502,6 @@ __global__ void k_split_prims(DevParams P, State<R> g, int gpitch, R* prim, size
         pr[VMU] = R(chem_potential(P, w.C, g.C[q + 1], g.C[q - 1], g.C[q + gpitch], g.C[q - gpitch]));
 #pragma unroll
     for (int k = 0; k <= NPRIM; ++k) prim[k * pstride + q] = pr[k];
-}
-
-// Derivative weights (MESH_GM, MESH_G0, MESH_GP) of ghosted index l.
-template <typename R>
-__device__ __forceinline__ void mesh_grad(const double* m, int stride, int l, R c[3])
-{
-    c[0] = R(m[MESH_GM * stride + l]);
-    c[1] = R(m[MESH_G0 * stride + l]);
-    c[2] = R(m[MESH_GP * stride + l]);
 }
 
 // The split kernels launch 64x4 threads; the bound lets the face and update
@@ -772,16 +835,27 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* part
 // ---------------------------------------------------------------------------
 static inline dim3 grid2(int nx, int ny, dim3 b) { return dim3((nx + b.x - 1) / b.x, (ny + b.y - 1) / b.y); }
 
-template <typename R, int LAT, int FAST, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY, bool NU = false>
 static hipError_t launch_fused_t(const DevParams& P, const StageCoef& K, const State<R>& in, const State<R>& Wn,
                                  const State<R>& out, R* fsdot, hipStream_t st)
 {
     const int tiles_x = (P.nx + TX - 1) / TX, tiles_y = (P.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;
     const int per_xcd = (ntiles + NXCD - 1) / NXCD;
-    hipLaunchKernelGGL((k_stage_fused<R, LAT, FAST, TX, TY>), dim3(per_xcd * NXCD), dim3(TX * TY), 0, st, P, K, in,
-                       Wn, out, fsdot, tiles_x, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_stage_fused<R, LAT, FAST, TX, TY, NU>), dim3(per_xcd * NXCD), dim3(TX * TY), 0, st, P, K,
+                       in, Wn, out, fsdot, tiles_x, ntiles, per_xcd);
     return hipGetLastError();
+}
+
+// Stretched meshes: one tile shape (NU_TX x NU_TY) and no FAST_HALF (delta_t
+// is not half of every width).
+template <typename R, int LAT>
+static hipError_t launch_fused_nu(const DevParams& P, const StageCoef& K, const State<R>& in, const State<R>& Wn,
+                                  const State<R>& out, R* fsdot, hipStream_t st)
+{
+    if (P.fast & FAST_UCP)
+        return launch_fused_t<R, LAT, FAST_UCP, NU_TX, NU_TY, true>(P, K, in, Wn, out, fsdot, st);
+    return launch_fused_t<R, LAT, 0, NU_TX, NU_TY, true>(P, K, in, Wn, out, fsdot, st);
 }
 
 template <typename R, int LAT, int FAST>
@@ -815,6 +889,10 @@ template <typename R>
 hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,
                               const State<R>& Wn, const State<R>& out, R* fsdot, hipStream_t st)
 {
+    if (P.mside) {
+        if (P.lattice_hg == 5) return launch_fused_nu<R, 5>(P, K, in, Wn, out, fsdot, st);
+        return launch_fused_nu<R, 9>(P, K, in, Wn, out, fsdot, st);
+    }
     if (P.lattice_hg == 5) return launch_fused_l<R, 5>(P, tile, K, in, Wn, out, fsdot, st);
     return launch_fused_l<R, 9>(P, tile, K, in, Wn, out, fsdot, st);
 }

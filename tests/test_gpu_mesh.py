@@ -1,5 +1,6 @@
-"""Stretched tensor-product meshes on the GPU (split kernels) vs the FP64 CPU
-oracle, through the C ABI.
+"""Stretched tensor-product meshes on the GPU (the fused kernel with its one
+stretched-mesh tile shape, and the split kernels) vs the FP64 CPU oracle,
+through the C ABI.
 
 Same tolerances as on uniform meshes: one residual evaluation agrees to
 1e-12 of each component's largest magnitude (1e-11 for the residual itself),
@@ -102,7 +103,7 @@ def test_fluxes_and_residual_match_oracle(oracle, name, pr):
     R_ref, Fx_ref, Fy_ref = oracle.residual(pr, W, fs)
     s = E.Solver(pr, st, kernel=E.KERNEL_AUTO)
     try:
-        assert s.schedule()[0] == E.KERNEL_SPLIT  # AUTO picks the split kernels on a stretched mesh
+        assert s.schedule() == (E.KERNEL_FUSED, 32, 16)  # one fused tile shape on a stretched mesh
         w6 = s.conserved()
         w6[5] = fs
         s.set_conserved(w6)
@@ -116,22 +117,28 @@ def test_fluxes_and_residual_match_oracle(oracle, name, pr):
 
 @pytest.mark.parametrize("name,pr", CASES, ids=IDS)
 def test_steps_match_oracle(oracle, name, pr):
+    """3 steps on the fused and the split kernels: both equal to the oracle and
+    to each other (partial 32x16 tiles in both directions on every case)."""
     st = PB.seeded_fields(pr, seed=21, amp=0.5)
     Wref, fsref = oracle.run(pr, st, 3)
-    s = E.Solver(pr, st, kernel=E.KERNEL_SPLIT)
-    try:
-        s.step(3)
-        w6 = s.conserved()
-        d = s.diagnostics()
-    finally:
-        s.close()
-    errs = field_errors(w6[:5], Wref)
-    assert max(errs.values()) < 1e-12, (name, errs)
-    assert np.abs(w6[5] - fsref).max() <= 1e-12 * max(1.0, np.abs(fsref).max())
     dref = oracle.diagnostics(pr, Wref)
-    assert d["mass"] == pytest.approx(dref[0], rel=1e-12)
-    assert d["volume_C"] == pytest.approx(dref[1], rel=1e-12)
-    assert d["solid"] == pytest.approx(dref[3], rel=1e-12, abs=1e-14)
+    out = []
+    for kernel in (E.KERNEL_FUSED, E.KERNEL_SPLIT):
+        s = E.Solver(pr, st, kernel=kernel)
+        try:
+            s.step(3)
+            w6 = s.conserved()
+            d = s.diagnostics()
+        finally:
+            s.close()
+        errs = field_errors(w6[:5], Wref)
+        assert max(errs.values()) < 1e-12, (name, kernel, errs)
+        assert np.abs(w6[5] - fsref).max() <= 1e-12 * max(1.0, np.abs(fsref).max())
+        assert d["mass"] == pytest.approx(dref[0], rel=1e-12)
+        assert d["volume_C"] == pytest.approx(dref[1], rel=1e-12)
+        assert d["solid"] == pytest.approx(dref[3], rel=1e-12, abs=1e-14)
+        out.append(w6)
+    assert np.abs(out[0] - out[1]).max() <= 1e-13 * np.abs(out[1]).max()
 
 
 def _graded_drop(nx=150, ny=97, precision=0):
@@ -154,13 +161,14 @@ def _graded_drop(nx=150, ny=97, precision=0):
     return pr, st
 
 
-def test_graded_drop_500_steps(oracle):
+@pytest.mark.parametrize("kernel", [E.KERNEL_AUTO, E.KERNEL_SPLIT])
+def test_graded_drop_500_steps(oracle, kernel):
     """Freezing sessile drop with a hysteresis window on a graded mesh:
     whole-run parity after 500 steps and the integrals."""
     pr, st = _graded_drop()
     oracle.set_threads(16)
     Wref, _ = oracle.run(pr, st, 500)
-    s = E.Solver(pr, st, kernel=E.KERNEL_AUTO)
+    s = E.Solver(pr, st, kernel=kernel)
     try:
         s.step(500)
         w6 = s.conserved()
@@ -177,11 +185,12 @@ def test_graded_drop_500_steps(oracle):
     assert d["solid"] == pytest.approx(dref[3], rel=1e-10)
 
 
-def test_graded_drop_fp32_within_1e4(oracle):
+@pytest.mark.parametrize("kernel", [E.KERNEL_FUSED, E.KERNEL_SPLIT])
+def test_graded_drop_fp32_within_1e4(oracle, kernel):
     pr, st = _graded_drop(precision=1)
     oracle.set_threads(16)
     Wref, _ = oracle.run(pr, st, 300)
-    s = E.Solver(pr, st, kernel=E.KERNEL_SPLIT)
+    s = E.Solver(pr, st, kernel=kernel)
     try:
         s.step(300)
         w6 = s.conserved()
@@ -192,25 +201,33 @@ def test_graded_drop_fp32_within_1e4(oracle):
 
 
 def test_large_stretched_grid_matches_oracle(oracle):
-    """1024 x 512 cells (several thousand 64x4 blocks, ragged against none of
-    the launch shapes but with every wall), a few steps compared cell by cell."""
-    pr, st = _graded_drop(nx=1024, ny=512)
+    """1030 x 517 cells (1056 fused tiles, partial ones in both directions, and
+    every wall), a few steps compared cell by cell, fused and split."""
+    pr, st = _graded_drop(nx=1030, ny=517)
     oracle.set_threads(16)
     Wref, _ = oracle.run(pr, st, 4)
-    s = E.Solver(pr, st, kernel=E.KERNEL_SPLIT)
-    try:
-        s.step(4)
-        w6 = s.conserved()
-    finally:
-        s.close()
-    assert scaled_err(w6[:5], Wref).max() < 1e-12
+    for kernel in (E.KERNEL_FUSED, E.KERNEL_SPLIT):
+        s = E.Solver(pr, st, kernel=kernel)
+        try:
+            s.step(4)
+            w6 = s.conserved()
+        finally:
+            s.close()
+        assert scaled_err(w6[:5], Wref).max() < 1e-12, kernel
 
 
-def test_fused_kernel_and_batch_refuse_a_stretched_mesh():
+def test_schedules_and_the_batch_refusal():
+    """AUTO and FUSED (whatever tile is asked) run the one stretched-mesh tile,
+    SPLIT the split kernels; the batch API refuses a stretched mesh."""
     pr, st = _graded_drop(nx=40, ny=30)
-    with pytest.raises(E.EulbfsError) as ei:
-        E.Solver(pr, st, kernel=E.KERNEL_FUSED)
-    assert ei.value.code == E.ENOTSUP
+    for kernel, tile, want in ((E.KERNEL_AUTO, (0, 0), (E.KERNEL_FUSED, 32, 16)),
+                               (E.KERNEL_FUSED, (64, 4), (E.KERNEL_FUSED, 32, 16)),
+                               (E.KERNEL_SPLIT, (0, 0), (E.KERNEL_SPLIT, 0, 0))):
+        s = E.Solver(pr, st, kernel=kernel, tile=tile)
+        try:
+            assert s.schedule() == want
+        finally:
+            s.close()
     b = E.Batch(hbm_budget=1 << 26, max_slots=2, precision=E.FP64)
     try:
         with pytest.raises(E.EulbfsError) as ei:
