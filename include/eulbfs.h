@@ -159,9 +159,8 @@ typedef struct {
  * Widths must be finite and > 0; both arrays are copied by eulbfs_create and
  * may be freed afterwards.  FUSED and AUTO run such a mesh on the fused kernel
  * with 32x16 tiles (tile_x and tile_y are ignored, nothing is autotuned),
- * SPLIT on the split kernels; the batch API refuses it (EULBFS_ENOTSUP;
- * eulbfs_batch_request_bytes returns 0).  Diagnostic integrals weight each
- * cell by w_i h_j and the tip height by h_j. */
+ * SPLIT on the split kernels; a batch steps it with the same 32x16 tiles.
+ * Diagnostic integrals weight each cell by w_i h_j and the tip height by h_j. */
 
 /* Initial state. */
 #define EULBFS_INIT_PRIMITIVE 0 /* 6 planes: T, F_l, C, u, v, p                */

@@ -732,7 +732,9 @@ namespace {
 
 void free_solver(eulbfs_solver* h, bool sync);
 
-// eulbfs_create; with sync = false the initial state is only enqueued.
+// eulbfs_create; with sync = false the initial state is only enqueued, and a
+// stretched mesh's tables must already be on their way to the workspace (the
+// batch stages them through pinned memory).
 int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws, size_t ws_bytes, void* hip_stream,
                   bool sync, eulbfs_solver** out)
 {
@@ -766,11 +768,13 @@ int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
         h->own_ws = true;
     }
     if (L.mesh_bytes) {
-        const std::vector<double> t = mesh_tables(prm, L);
-        hipError_t he = hipMemcpy(h->ws + L.mesh, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice);
-        if (he != hipSuccess) {
-            free_solver(h, false);
-            return set_err(err, EULBFS_EDEVICE, std::string("hipMemcpy (mesh tables): ") + hipGetErrorString(he));
+        if (sync) {
+            const std::vector<double> t = mesh_tables(prm, L);
+            hipError_t he = hipMemcpy(h->ws + L.mesh, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (he != hipSuccess) {
+                free_solver(h, false);
+                return set_err(err, EULBFS_EDEVICE, std::string("hipMemcpy (mesh tables): ") + hipGetErrorString(he));
+            }
         }
         const double* base = (const double*)(h->ws + L.mesh);
         h->dp.mside = base;
@@ -1053,12 +1057,12 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     if (b->upload_done[par]) HIP_TRY(hipEventSynchronize(b->upload_done[par]));
     BatchDesc<R>* hd = reinterpret_cast<BatchDesc<R>*>(b->h_desc[par]);
     int* ht = b->h_tiles[par];
-    // tiles grouped by lattice and fast-path flags: one launch per group
-    // present, each on its own sub-list of tiles, so a request's first tile
-    // is counted from the start of its group
-    constexpr int NGROUP = 8;
+    // tiles grouped by mesh kind, lattice and fast-path flags: one launch per
+    // group present, each on its own sub-list of tiles, so a request's first
+    // tile is counted from the start of its group
+    constexpr int NGROUP = 16;
     auto group_of = [](const eulbfs_solver* h) {
-        return (h->prm.lattice_hg == 5 ? 4 : 0) + (h->dp.fast & (FAST_HALF | FAST_UCP));
+        return (h->dp.mside ? 8 : 0) + (h->prm.lattice_hg == 5 ? 4 : 0) + (h->dp.fast & (FAST_HALF | FAST_UCP));
     };
     int ntiles[NGROUP] = {}, first[NGROUP] = {}, nd = 0;
     std::vector<int> order;
@@ -1094,8 +1098,8 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
         for (int stage = 0; stage < 3; ++stage)
             for (int g = 0; g < NGROUP; ++g)
                 if (ntiles[g])
-                    HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g], g >= 4 ? 5 : 9, g & 3,
-                                                    K[stage], stage, b->stream));
+                    HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g], (g & 4) ? 5 : 9,
+                                                    g & 3, g >= 8, K[stage], stage, b->stream));
     // requests finished by this tick: their FP64 sums go to pinned memory
     for (int k : act) {
         Slot& sl = b->slots[k];
@@ -1161,7 +1165,7 @@ extern "C" {
 
 size_t eulbfs_batch_request_bytes(const eulbfs_params* prm)
 {
-    if (!check(prm).empty() || stretched(prm)) return 0;
+    if (!check(prm).empty()) return 0;
     const eulbfs_params p = batch_view(prm);
     return align_up(make_layout(&p).total);
 }
@@ -1241,7 +1245,6 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
     *slot = -1;
     const std::string e = check(prm);
     if (!e.empty()) return set_err(err, EULBFS_EINVAL, e);
-    if (stretched(prm)) return set_err(err, EULBFS_ENOTSUP, "the batch runs uniform meshes only");
     if (prm->precision != b->precision) return set_err(err, EULBFS_EINVAL, "request precision differs from the batch");
     if (nsteps <= 0) return set_err(err, EULBFS_EINVAL, "nsteps must be > 0");
     int k = 0;
@@ -1257,6 +1260,14 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
     // request's own staging area (its arena range is idle: a freed range is
     // only reused once its last tick has completed), so admission does not
     // wait for the ticks in flight; the batch stream waits for the copy.
+    if (L.mesh_bytes) {  // stretched mesh: its tables take the same route
+        const std::vector<double> t = mesh_tables(&p, L);
+        const int rc = admit_stage(b, t.data(), t.size(), b->arena + off + L.mesh);
+        if (rc != EULBFS_OK) {
+            arena_free(b, off, bytes);
+            return rc;
+        }
+    }
     eulbfs_init dinit = *init;
     if (!init->on_device) {
         const size_t n6 = (size_t)6 * p.nx * p.ny;

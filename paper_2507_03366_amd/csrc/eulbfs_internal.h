@@ -37,8 +37,10 @@ constexpr int BATCH_TX = 32, BATCH_TY = 16;
 
 // Tile of the fused stage kernel on a stretched mesh (one shape is compiled:
 // its face loop holds the mesh weights beside the bases, which a 1024-thread
-// tile could not keep within its 128 VGPRs).
+// tile could not keep within its 128 VGPRs).  The batched kernel runs
+// stretched requests with its own tile, the same shape.
 constexpr int NU_TX = 32, NU_TY = 16;
+static_assert(NU_TX == BATCH_TX && NU_TY == BATCH_TY, "a stretched request steps alike alone and in a batch");
 
 // One request of a batch: its constants, its three copies of W (W^n, W1, W2)
 // and its dF_s/dt plane, and where its tiles start in the batch's tile list.
@@ -70,7 +72,7 @@ hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, 
                          hipStream_t st);
 template <typename R>
 hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
-                                const StageCoef& K, int stage, hipStream_t st);
+                                bool nu, const StageCoef& K, int stage, hipStream_t st);
 template <typename R>
 hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,
                          hipStream_t st);

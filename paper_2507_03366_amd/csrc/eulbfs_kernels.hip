@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(TX* TY)
 // tiles go to one XCD, as in k_stage_fused.  (A persistent grid looping over
 // the tiles held more registers per thread, one wave fewer per SIMD in FP32,
 // and ran 20-30 % slower.)
-template <typename R, int LAT, int FAST, int TX, int TY>
+template <typename R, int LAT, int FAST, int TX, int TY, bool NU = false>
 __global__ void __launch_bounds__(TX* TY)
     k_stage_batched(const BatchDesc<R>* __restrict__ descs, const int* __restrict__ tile_req, int ntiles,
                     StageCoef K, int stage)
@@ -457,8 +457,8 @@ __global__ void __launch_bounds__(TX* TY)
     const int lt = t - D.tile0;  // tile index within its request, 0 <= lt < tiles of the request
     const State<R>& in = D.W[stage];
     const State<R>& out = D.W[stage == 2 ? 0 : stage + 1];
-    stage_tile<R, LAT, FAST, TX, TY>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX,
-                                     (lt / D.tiles_x) * TY);
+    stage_tile<R, LAT, FAST, TX, TY, NU>(D.P, K, in, D.W[0], out, D.fsdot, (lt % D.tiles_x) * TX,
+                                         (lt / D.tiles_x) * TY);
 }
 
 // ---------------------------------------------------------------------------
@@ -897,22 +897,34 @@ hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, 
     return launch_fused_l<R, 9>(P, tile, K, in, Wn, out, fsdot, st);
 }
 
-template <typename R, int LAT, int FAST>
+template <typename R, int LAT, int FAST, bool NU = false>
 static void launch_batched_t(const BatchDesc<R>* descs, const int* tile_req, int ntiles, const StageCoef& K,
                              int stage, hipStream_t st)
 {
     const int per_xcd = (ntiles + NXCD - 1) / NXCD;
-    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, BATCH_TX, BATCH_TY>), dim3(per_xcd * NXCD),
+    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, BATCH_TX, BATCH_TY, NU>), dim3(per_xcd * NXCD),
                        dim3(BATCH_TX * BATCH_TY), 0, st, descs, tile_req, ntiles, K, stage);
 }
 
-// Requests of one batched launch share the lattice and the fast-path flags.
+// Requests of one batched launch share the mesh kind, the lattice and the
+// fast-path flags (a stretched mesh never has FAST_HALF).
 template <typename R>
 hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
-                                const StageCoef& K, int stage, hipStream_t st)
+                                bool nu, const StageCoef& K, int stage, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     const int f = fast & (FAST_HALF | FAST_UCP);
+    if (nu) {
+        const bool ucp = (f & FAST_UCP) != 0;
+        if (lattice == 5) {
+            if (ucp) launch_batched_t<R, 5, FAST_UCP, true>(descs, tile_req, ntiles, K, stage, st);
+            else launch_batched_t<R, 5, 0, true>(descs, tile_req, ntiles, K, stage, st);
+        } else {
+            if (ucp) launch_batched_t<R, 9, FAST_UCP, true>(descs, tile_req, ntiles, K, stage, st);
+            else launch_batched_t<R, 9, 0, true>(descs, tile_req, ntiles, K, stage, st);
+        }
+        return hipGetLastError();
+    }
 #define EULBFS_BATCHED(LATV)                                                                                    \
     switch (f) {                                                                                                \
         case FAST_HALF: launch_batched_t<R, LATV, FAST_HALF>(descs, tile_req, ntiles, K, stage, st); break;      \
@@ -1013,8 +1025,8 @@ hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial,
                                                 hipStream_t);                                                      \
     template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
     template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);   \
-    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, const StageCoef&,  \
-                                                int, hipStream_t);
+    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, bool,              \
+                                                const StageCoef&, int, hipStream_t);
 
 EULBFS_INSTANTIATE(double)
 EULBFS_INSTANTIATE(float)

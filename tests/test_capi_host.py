@@ -129,8 +129,8 @@ def test_create_rejects_before_touching_the_device():
 
 def test_stretched_mesh_parameters():
     """Widths must be finite and > 0; delta_t is bounded by half the smallest
-    width; the workspace holds the mesh tables beside the uniform mesh's; the
-    batch API sizes nothing for a stretched mesh."""
+    width; a solver's workspace and a batch request hold the mesh tables
+    beside what the uniform mesh needs."""
     import numpy as np
 
     pr, _ = PB.static_droplet(n=64, R=16)
@@ -139,7 +139,8 @@ def test_stretched_mesh_parameters():
     assert E.eulbfs_check_params(P) == ""
     uni = E.eulbfs_workspace_bytes(E.params_from_problem(pr.replace(delta_t=0.3), kernel=E.KERNEL_AUTO))
     assert uni < E.eulbfs_workspace_bytes(P) < uni + (1 << 20)
-    assert E.eulbfs_batch_request_bytes(P) == 0
+    uni_req = E.eulbfs_batch_request_bytes(E.params_from_problem(pr.replace(delta_t=0.3)))
+    assert uni_req < E.eulbfs_batch_request_bytes(P) < uni_req + (1 << 20)
     P = E.params_from_problem(pr.replace(y_width=w, delta_t=0.31), kernel=E.KERNEL_SPLIT)
     assert "delta_t" in E.eulbfs_check_params(P)
     bad = w.copy()

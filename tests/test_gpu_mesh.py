@@ -216,9 +216,9 @@ def test_large_stretched_grid_matches_oracle(oracle):
         assert scaled_err(w6[:5], Wref).max() < 1e-12, kernel
 
 
-def test_schedules_and_the_batch_refusal():
+def test_schedules():
     """AUTO and FUSED (whatever tile is asked) run the one stretched-mesh tile,
-    SPLIT the split kernels; the batch API refuses a stretched mesh."""
+    SPLIT the split kernels."""
     pr, st = _graded_drop(nx=40, ny=30)
     for kernel, tile, want in ((E.KERNEL_AUTO, (0, 0), (E.KERNEL_FUSED, 32, 16)),
                                (E.KERNEL_FUSED, (64, 4), (E.KERNEL_FUSED, 32, 16)),
@@ -228,13 +228,46 @@ def test_schedules_and_the_batch_refusal():
             assert s.schedule() == want
         finally:
             s.close()
-    b = E.Batch(hbm_budget=1 << 26, max_slots=2, precision=E.FP64)
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.FP32])
+def test_batch_with_stretched_and_uniform_requests(oracle, precision):
+    """Two stretched requests (the graded drop and a D2Q5 box with hysteresis
+    walls) and a uniform one in one batch: each equals its own solo fused run
+    bit for bit (the batched kernel's tile is the stretched-mesh tile) and, in
+    FP64, the oracle to 1e-10 (the whole-run bar: the uniform droplet's light
+    gas carries its momentum differences to 6e-12 within 50 steps)."""
+    import torch
+
+    drop, drop_st = _graded_drop(precision=precision)
+    box = CASES[1][1].replace(lattice_hg=5, precision=precision)
+    box_st = PB.seeded_fields(box, seed=4, amp=0.5)
+    uni, uni_st = PB.static_droplet(n=64, R=16)
+    uni = uni.replace(precision=precision)
+    reqs = [(drop, drop_st, 60), (box, box_st, 40), (uni, uni_st, 50)]
+    b = E.Batch(1 << 28, 8, precision=precision, stream=torch.cuda.Stream())
     try:
-        with pytest.raises(E.EulbfsError) as ei:
-            b.admit(pr, st, 10)
-        assert ei.value.code == E.ENOTSUP
+        slots = [b.admit(pr, st, n) for pr, st, n in reqs]
+        assert all(sl is not None for sl in slots)
+        while any(b.diagnostics(sl)["steps"] < n for sl, (_, _, n) in zip(slots, reqs)):
+            b.tick(10)
+        torch.cuda.synchronize()
+        mix = [b.conserved(sl) for sl in slots]
     finally:
         b.close()
+    oracle.set_threads(16)
+    for (pr, st, n), w in zip(reqs, mix):
+        s = E.Solver(pr, st, kernel=E.KERNEL_FUSED, tile=(32, 16))
+        try:
+            s.step(n)
+            solo = s.conserved()
+        finally:
+            s.close()
+        assert np.array_equal(w, solo), pr.nx
+        if precision == E.FP64:
+            Wref, _ = oracle.run(pr, st, n)
+            errs = field_errors(w[:5], Wref)
+            assert max(errs.values()) < 1e-10, (pr.nx, errs)
 
 
 def test_two_phase_neumann_on_a_graded_mesh_on_gpu(oracle):
