@@ -16,7 +16,8 @@
  *
  * Conventions
  *   - Lattice units: cell size dx (default 1), c_s^2 = 1/3, streaming step
- *     delta_t with 0 < delta_t <= dx/2, fixed update step dt.
+ *     delta_t with 0 < delta_t <= dx/2 (half the smallest cell on a stretched
+ *     mesh), fixed update step dt.
  *   - Fields are planes of nx*ny values, row-major, x fastest (index
  *     j*nx + i, cell centre ((i+1/2) dx, (j+1/2) dx) on a uniform mesh).
  *   - Stretched meshes: optional column widths and row heights (see
