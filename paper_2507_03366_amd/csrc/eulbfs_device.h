@@ -52,8 +52,8 @@ struct DevParams {
     // FAST_UCP closure constants: H_s = C_p T_s, H_l = C_p T_l + L, 1/C_p,
     // 1/(H_l - H_s) (0 without a mushy range)
     double Hs_u, Hl_u, inv_cp, inv_dH;
-    // Stretched tensor-product mesh (split kernels only); all NULL on a
-    // uniform mesh.  mside: per side, MS_STRIDE doubles (MS_*).  mxc, myc:
+    // Stretched tensor-product mesh (the NU variants of the kernels); all
+    // NULL on a uniform mesh.  mside: per side, MS_STRIDE doubles (MS_*).  mxc, myc:
     // NMESH arrays (MESH_*) over the ghosted columns / rows, msx / msy apart.
     const double* mside;
     const double* mxc;

@@ -7,12 +7,13 @@
 //                   mu_c, computes every face flux of the tile once (Eqs.
 //                   53-56), then updates its cells with the sources of Eq. (51),
 //                   the RK combination and the momentum projection.
+//   k_stage_batched the same tile body over the tiles of every grid of a batch.
 //   k_fill_ghosts / k_split_prims / k_split_faces / k_split_update
 //                   the same stage in four kernels with the intermediate
 //                   fields in HBM (ghosted state, primitive planes, face flux
-//                   planes); used for face-by-face checks, as a variant,
-//                   and for stretched meshes (NU: per-column and per-row
-//                   geometry tables instead of one dx).
+//                   planes); used for face-by-face checks and as a variant.
+// Each stage kernel has a stretched-mesh variant (template flag NU) that takes
+// the geometry from per-column and per-row tables instead of one dx.
 //   k_init          primitive initial fields -> conserved vector.
 //   k_export        conserved or derived field -> dense double plane.
 //   k_reduce_*      FP64 integrals, deterministic two-pass wave reduction.
