@@ -39,3 +39,20 @@ def test_bench_json_line():
     assert d["serving"]["batched_fp32_burst"]["failed"] == []
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
+
+
+@pytest.mark.gpu
+def test_bench_stretched_workload():
+    """The graded-mesh droplet runs through the same contract (fused 32x16
+    tiles, a CPU baseline from the oracle on the same stretched mesh)."""
+    r = subprocess.run([sys.executable, "-u", str(ROOT / "bench.py"), "--workload", "G512", "--steps", "3",
+                        "--warmup", "1", "--serving", "0", "--cpu-budget", "1"],
+                       capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    assert "stretched mesh" in d["config"]["workload"] and d["value"] > 0
+    assert d["config"]["schedule"] == {"kernel": "fused", "tile": "32x16"}
+    assert d["diagnostics_after"]["nonfinite"] == 0
+    assert d["cpu_baseline"]["value"] > 0
