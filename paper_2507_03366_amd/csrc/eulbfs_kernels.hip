@@ -137,7 +137,26 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     R* sF = reinterpret_cast<R*>(sU);                                          // 5 planes of NFX+NFY
 
     const int tid = threadIdx.x;
+    // NU: the mesh weights (MESH_*) of the W2 columns and H2 rows of the tile
+    // and two halo layers, staged once per tile in FP64 (mu_c is formed in
+    // FP64 whatever the field type)
+    constexpr int NMW = NU ? NMESH * (W2 + H2) : 1;
+    __shared__ double sMesh[NMW];
+    auto mx = [&](int k, int li) { return sMesh[k * W2 + li]; };
+    auto my = [&](int k, int lj) { return sMesh[NMESH * W2 + k * H2 + lj]; };
+    // ghosted column / row index of the tile + 2 layers (li, lj in [0, W2)),
+    // clamped to the rows of the tables that hold derivative weights
+    auto gcol = [&](int li) { return min(i0 + li + 1, P.nx + 2 * NG - 2); };
+    auto grow = [&](int lj) { return min(j0 + lj + 1, P.ny + 2 * NG - 2); };
     __syncthreads();  // the LDS of a previous tile of this workgroup is free
+    if constexpr (NU) {
+        for (int t = tid; t < NMW; t += NT) {
+            if (t < NMESH * W2)
+                sMesh[t] = P.mxc[(t / W2) * P.msx + gcol(t % W2)];
+            else
+                sMesh[t] = P.myc[((t - NMESH * W2) / H2) * P.msy + grow((t - NMESH * W2) % H2)];
+        }
+    }
 
     // 1. stage W of the tile and three halo layers (boundary rules only for
     // tiles whose halo leaves the grid)
@@ -246,11 +265,6 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     }
     __syncthreads();
 
-    // ghosted column / row index of the tile + 2 layers (li, lj in [0, W2)),
-    // clamped to the rows of the tables that hold derivative weights
-    auto gcol = [&](int li) { return min(i0 + li + 1, P.nx + 2 * NG - 2); };
-    auto grow = [&](int lj) { return min(j0 + lj + 1, P.ny + 2 * NG - 2); };
-
     // 2. primitives and mu_c on the tile and two halo layers
     for (int q = tid; q < W2 * H2; q += NT) {
         const int li = q % W2, lj = q / W2;
@@ -263,10 +277,11 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
         w.C = sC[q3];
         R pr[NPRIM + 1];
         primitives<R, FAST>(P, w, pr);
-        if (NU)
-            pr[VMU] = R(chem_potential_nu(P, gcol(li), grow(lj), w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3],
-                                          sC[q3 - W3]));
-        else
+        if (NU) {  // chem_potential_nu with the staged weights
+            const double lap = mx(MESH_LM, li) * sC[q3 - 1] + mx(MESH_L0, li) * w.C + mx(MESH_LP, li) * sC[q3 + 1] +
+                               my(MESH_LM, lj) * sC[q3 - W3] + my(MESH_L0, lj) * w.C + my(MESH_LP, lj) * sC[q3 + W3];
+            pr[VMU] = R(2.0 * P.beta * w.C * (w.C - 1.0) * (2.0 * w.C - 1.0) - P.kappa * lap);
+        } else
             pr[VMU] = R(chem_potential(P, w.C, sC[q3 + 1], sC[q3 - 1], sC[q3 + W3], sC[q3 - W3]));
 #pragma unroll
         for (int k = 0; k < L::NPL; ++k) sP[k][q] = pr[k];
@@ -304,12 +319,10 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             const int fi = f % (TX + 1), fj = f / (TX + 1);
             const int a = (fj + 2) * W2 + fi + 1;
             if (NU) {
-                R ca[3], cb[3], ct[3];
-                const int la = gcol(fi + 1), lb = gcol(fi + 2);
-                mesh_grad(P.mxc, P.msx, la, ca);
-                mesh_grad(P.mxc, P.msx, lb, cb);
-                mesh_grad(P.myc, P.msy, grow(fj + 2), ct);
-                const R ha = R(P.mxc[MESH_HW * P.msx + la]), hb = R(P.mxc[MESH_HW * P.msx + lb]);
+                const R ca[3] = {R(mx(MESH_GM, fi + 1)), R(mx(MESH_G0, fi + 1)), R(mx(MESH_GP, fi + 1))};
+                const R cb[3] = {R(mx(MESH_GM, fi + 2)), R(mx(MESH_G0, fi + 2)), R(mx(MESH_GP, fi + 2))};
+                const R ct[3] = {R(my(MESH_GM, fj + 2)), R(my(MESH_G0, fj + 2)), R(my(MESH_GP, fj + 2))};
+                const R ha = R(mx(MESH_HW, fi + 1)), hb = R(mx(MESH_HW, fi + 2));
 #pragma unroll
                 for (int k = 0; k < NPRIM; ++k)
                     face_bases_nu(sP[k], a, 1, W2, ca, cb, ct, ha, hb, ds, X.A[k], X.B[k], X.M[k], X.da[k],
@@ -335,12 +348,10 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             const int fi = g % TX, fj = g / TX;
             const int a = (fj + 1) * W2 + fi + 2;
             if (NU) {
-                R ca[3], cb[3], ct[3];
-                const int la = grow(fj + 1), lb = grow(fj + 2);
-                mesh_grad(P.myc, P.msy, la, ca);
-                mesh_grad(P.myc, P.msy, lb, cb);
-                mesh_grad(P.mxc, P.msx, gcol(fi + 2), ct);
-                const R ha = R(P.myc[MESH_HW * P.msy + la]), hb = R(P.myc[MESH_HW * P.msy + lb]);
+                const R ca[3] = {R(my(MESH_GM, fj + 1)), R(my(MESH_G0, fj + 1)), R(my(MESH_GP, fj + 1))};
+                const R cb[3] = {R(my(MESH_GM, fj + 2)), R(my(MESH_G0, fj + 2)), R(my(MESH_GP, fj + 2))};
+                const R ct[3] = {R(mx(MESH_GM, fi + 2)), R(mx(MESH_G0, fi + 2)), R(mx(MESH_GP, fi + 2))};
+                const R ha = R(my(MESH_HW, fj + 1)), hb = R(my(MESH_HW, fj + 2));
 #pragma unroll
                 for (int k = 0; k < NPRIM; ++k) {
                     const int ks = k == VU ? VV : (k == VV ? VU : k);  // local frame n = y, t = x
@@ -390,8 +401,8 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     const int fl = ty * (TX + 1) + tx;
     const int fb = NFX + ty * TX + tx;
     // Eq. (52) on a Cartesian cell: (1/V) S = 1/width along each direction
-    const R idx = NU ? R(P.mxc[MESH_IW * P.msx + i + NG]) : R(1.0 / P.dx);
-    const R idy = NU ? R(P.myc[MESH_IW * P.msy + j + NG]) : idx;
+    const R idx = NU ? R(mx(MESH_IW, tx + 2)) : R(1.0 / P.dx);
+    const R idy = NU ? R(my(MESH_IW, ty + 2)) : idx;
     R dF[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k)
@@ -403,9 +414,8 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     c[NPRIM] = plane_rho<R, RHO>(P, sP, c2);
     R dudx, dvdy, drx, dry, dmx, dmy;
     if (NU) {
-        R gx[3], gy[3];
-        mesh_grad(P.mxc, P.msx, i + NG, gx);
-        mesh_grad(P.myc, P.msy, j + NG, gy);
+        const R gx[3] = {R(mx(MESH_GM, tx + 2)), R(mx(MESH_G0, tx + 2)), R(mx(MESH_GP, tx + 2))};
+        const R gy[3] = {R(my(MESH_GM, ty + 2)), R(my(MESH_G0, ty + 2)), R(my(MESH_GP, ty + 2))};
         dudx = gx[0] * sP[VU][c2 - 1] + gx[1] * sP[VU][c2] + gx[2] * sP[VU][c2 + 1];
         dvdy = gy[0] * sP[VV][c2 - W2] + gy[1] * sP[VV][c2] + gy[2] * sP[VV][c2 + W2];
         drx = gx[0] * plane_rho<R, RHO>(P, sP, c2 - 1) + gx[1] * c[NPRIM] + gx[2] * plane_rho<R, RHO>(P, sP, c2 + 1);
