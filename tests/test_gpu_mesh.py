@@ -137,6 +137,10 @@ def test_steps_match_oracle(oracle, name, pr):
         assert d["mass"] == pytest.approx(dref[0], rel=1e-12)
         assert d["volume_C"] == pytest.approx(dref[1], rel=1e-12)
         assert d["solid"] == pytest.approx(dref[3], rel=1e-12, abs=1e-14)
+        # tip height: F_s of the middle column weighted by the row heights
+        _, wy = PB.widths(pr)
+        tip = float((oracle.primitives(pr, Wref)[2][:, pr.nx // 2] * wy).sum())
+        assert d["tip"] == pytest.approx(tip, rel=1e-12, abs=1e-14)
         out.append(w6)
     assert np.abs(out[0] - out[1]).max() <= 1e-13 * np.abs(out[1]).max()
 
