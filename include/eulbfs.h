@@ -246,7 +246,8 @@ int eulbfs_destroy(eulbfs_t h);
 
 /* The schedule a solver steps with: kernel is EULBFS_KERNEL_FUSED or _SPLIT
  * (AUTO resolves to FUSED), tile_x x tile_y the fused kernel's tile (the one
- * EULBFS_KERNEL_AUTO picked; 0 x 0 for the split kernels).  Any output
+ * EULBFS_KERNEL_AUTO picked, 32 x 16 on a stretched mesh; 0 x 0 for the split
+ * kernels).  Any output
  * pointer may be NULL.  Host call, no device work.  Returns EULBFS_EINVAL for
  * a NULL handle. */
 int eulbfs_schedule(eulbfs_t h, int32_t* kernel, int32_t* tile_x, int32_t* tile_y);
