@@ -70,7 +70,8 @@ extern "C" {
 #define EULBFS_KERNEL_AUTO 2  /* FUSED with the tile shape that create timed
                                  fastest on the initial state (cached per
                                  process for the grid, precision and lattice);
-                                 FUSED 32x16 on a stretched mesh */
+                                 FUSED 32x16 (FP64) or 32x32 (FP32) on a
+                                 stretched mesh */
 
 /* One side of the domain.  Sides are indexed 0: x-, 1: x+, 2: y-, 3: y+.
  * periodic must agree on opposite sides.  For a wall:
@@ -159,8 +160,9 @@ typedef struct {
  * angle reads dC/dn from the parabola through the first three cell centres.
  * Widths must be finite and > 0; both arrays are copied by eulbfs_create and
  * may be freed afterwards.  FUSED and AUTO run such a mesh on the fused kernel
- * with 32x16 tiles (tile_x and tile_y are ignored, nothing is autotuned),
- * SPLIT on the split kernels; a batch steps it with the same 32x16 tiles.
+ * with 32x16 tiles in FP64 and 32x32 in FP32 (tile_x and tile_y are ignored,
+ * nothing is autotuned), SPLIT on the split kernels; a batch steps it with its
+ * 32x16 tiles (every tile shape gives the same bits).
  * Diagnostic integrals weight each cell by w_i h_j and the tip height by h_j. */
 
 /* Initial state. */
@@ -246,8 +248,8 @@ int eulbfs_destroy(eulbfs_t h);
 
 /* The schedule a solver steps with: kernel is EULBFS_KERNEL_FUSED or _SPLIT
  * (AUTO resolves to FUSED), tile_x x tile_y the fused kernel's tile (the one
- * EULBFS_KERNEL_AUTO picked, 32 x 16 on a stretched mesh; 0 x 0 for the split
- * kernels).  Any output
+ * EULBFS_KERNEL_AUTO picked; on a stretched mesh 32 x 16 in FP64, 32 x 32 in
+ * FP32; 0 x 0 for the split kernels).  Any output
  * pointer may be NULL.  Host call, no device work.  Returns EULBFS_EINVAL for
  * a NULL handle. */
 int eulbfs_schedule(eulbfs_t h, int32_t* kernel, int32_t* tile_x, int32_t* tile_y);

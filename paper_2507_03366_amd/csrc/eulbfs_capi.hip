@@ -694,9 +694,11 @@ int setup_schedule(eulbfs_solver* h, const eulbfs_init* init)
         return EULBFS_OK;
     }
     h->sched = EULBFS_KERNEL_FUSED;
-    if (h->dp.mside) {  // a stretched mesh has one fused tile shape
-        static_assert(NU_TX == 32 && NU_TY == 16, "the stretched-mesh tile is reported as TILE_32x16");
-        h->tile = TILE_32x16;
+    if (h->dp.mside) {  // a stretched mesh has one fused tile shape per field type
+        static_assert(NuTile<double>::TX == 32 && NuTile<double>::TY == 16 && NuTile<float>::TX == 32 &&
+                          NuTile<float>::TY == 32,
+                      "the stretched-mesh tiles are reported as TILE_32x16 (FP64) and TILE_32x32 (FP32)");
+        h->tile = h->prm.precision == EULBFS_FP32 ? TILE_32x32 : TILE_32x16;
         return EULBFS_OK;
     }
     if (h->prm.kernel == EULBFS_KERNEL_AUTO) return autotune<R>(h, init);

@@ -35,12 +35,15 @@ constexpr int NXCD = 8;  // accelerator complex dies of an MI355X, each with its
 // solves/s).
 constexpr int BATCH_TX = 32, BATCH_TY = 16;
 
-// Tile of the fused stage kernel on a stretched mesh (one shape is compiled:
-// its face loop holds the mesh weights beside the bases, which a 1024-thread
-// tile could not keep within its 128 VGPRs).  The batched kernel runs
-// stretched requests with its own tile, the same shape.
-constexpr int NU_TX = 32, NU_TY = 16;
-static_assert(NU_TX == BATCH_TX && NU_TY == BATCH_TY, "a stretched request steps alike alone and in a batch");
+// Tile of the fused stage kernel on a stretched mesh, one shape per field
+// type: 32 x 16 in FP64, where a 1024-thread 32 x 32 tile would need 162 KB of
+// LDS and spill the mesh weights; 32 x 32 in FP32 (6-7 % faster than 32 x 16
+// at 512^2).  The batched kernel runs stretched requests with its own tile;
+// every tile shape gives the same bits.
+template <typename R>
+struct NuTile {
+    static constexpr int TX = 32, TY = sizeof(R) == 4 ? 32 : 16;
+};
 
 // One request of a batch: its constants, its three copies of W (W^n, W1, W2)
 // and its dF_s/dt plane, and where its tiles start in the batch's tile list.

@@ -858,15 +858,15 @@ static hipError_t launch_fused_t(const DevParams& P, const StageCoef& K, const S
     return hipGetLastError();
 }
 
-// Stretched meshes: one tile shape (NU_TX x NU_TY) and no FAST_HALF (delta_t
-// is not half of every width).
+// Stretched meshes: one tile shape per field type (NuTile) and no FAST_HALF
+// (delta_t is not half of every width).
 template <typename R, int LAT>
 static hipError_t launch_fused_nu(const DevParams& P, const StageCoef& K, const State<R>& in, const State<R>& Wn,
                                   const State<R>& out, R* fsdot, hipStream_t st)
 {
-    if (P.fast & FAST_UCP)
-        return launch_fused_t<R, LAT, FAST_UCP, NU_TX, NU_TY, true>(P, K, in, Wn, out, fsdot, st);
-    return launch_fused_t<R, LAT, 0, NU_TX, NU_TY, true>(P, K, in, Wn, out, fsdot, st);
+    constexpr int TX = NuTile<R>::TX, TY = NuTile<R>::TY;
+    if (P.fast & FAST_UCP) return launch_fused_t<R, LAT, FAST_UCP, TX, TY, true>(P, K, in, Wn, out, fsdot, st);
+    return launch_fused_t<R, LAT, 0, TX, TY, true>(P, K, in, Wn, out, fsdot, st);
 }
 
 template <typename R, int LAT, int FAST>

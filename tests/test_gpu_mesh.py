@@ -221,13 +221,14 @@ def test_large_stretched_grid_matches_oracle(oracle):
 
 
 def test_schedules():
-    """AUTO and FUSED (whatever tile is asked) run the one stretched-mesh tile,
-    SPLIT the split kernels."""
+    """AUTO and FUSED (whatever tile is asked) run the stretched-mesh tile of
+    the field type (32x16 in FP64, 32x32 in FP32), SPLIT the split kernels."""
     pr, st = _graded_drop(nx=40, ny=30)
-    for kernel, tile, want in ((E.KERNEL_AUTO, (0, 0), (E.KERNEL_FUSED, 32, 16)),
-                               (E.KERNEL_FUSED, (64, 4), (E.KERNEL_FUSED, 32, 16)),
-                               (E.KERNEL_SPLIT, (0, 0), (E.KERNEL_SPLIT, 0, 0))):
-        s = E.Solver(pr, st, kernel=kernel, tile=tile)
+    for kernel, tile, prec, want in ((E.KERNEL_AUTO, (0, 0), E.FP64, (E.KERNEL_FUSED, 32, 16)),
+                                     (E.KERNEL_FUSED, (64, 4), E.FP64, (E.KERNEL_FUSED, 32, 16)),
+                                     (E.KERNEL_AUTO, (0, 0), E.FP32, (E.KERNEL_FUSED, 32, 32)),
+                                     (E.KERNEL_SPLIT, (0, 0), E.FP64, (E.KERNEL_SPLIT, 0, 0))):
+        s = E.Solver(pr, st, kernel=kernel, tile=tile, precision=prec)
         try:
             assert s.schedule() == want
         finally:
@@ -238,7 +239,8 @@ def test_schedules():
 def test_batch_with_stretched_and_uniform_requests(oracle, precision):
     """Two stretched requests (the graded drop and a D2Q5 box with hysteresis
     walls) and a uniform one in one batch: each equals its own solo fused run
-    bit for bit (the batched kernel's tile is the stretched-mesh tile) and, in
+    bit for bit (every tile shape gives the same bits: the batch runs 32x16
+    tiles, a solo FP32 stretched request 32x32) and, in
     FP64, the oracle to 1e-10 (the whole-run bar: the uniform droplet's light
     gas carries its momentum differences to 6e-12 within 50 steps)."""
     import torch
