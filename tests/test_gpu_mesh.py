@@ -73,6 +73,12 @@ def _cases():
         **BASE)))
     cases.append(("periodic_both", PB.Problem(nx=16, ny=11, periodic_x=True, periodic_y=True, y_width=_w(11, 6),
                                               **BASE)))
+    # tenfold width ratios: random columns in [0.3, 3], rows graded from 0.3 to 3
+    strong = dict(BASE, delta_t=0.15, dt=0.05)
+    cases.append(("ratio10", PB.Problem(nx=45, ny=40, x_width=_w(45, 7, 0.3, 3.0),
+                                        y_width=PB.graded_widths(40, 0.3, 1.1, 3.0), walls={
+        "x-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -1.0, 75.0), "x+": PB.Wall(PB.NOSLIP, PB.ADIABATIC, 0.0, 100.0),
+        "y-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -0.5, 60.0, 80.0, 50.0), "y+": PB.Wall(PB.FREESLIP)}, **strong)))
     return cases
 
 
