@@ -45,20 +45,20 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_internal.h, csrc/eulbfs_kernels.hip and
 # build.py).
-COUNTS_FINGERPRINT = "944d596c5c38f088"
+COUNTS_FINGERPRINT = "e08cb260e4d5e144"
 COUNTS = {
-    "fp64/32x8": {"f64": 1237.2, "valu": 1235.4, "hbm": 31886680},
-    "fp64/64x4": {"f64": 1257.8, "valu": 1281.5, "hbm": 31897429},
-    "fp64/16x16": {"f64": 1237.6, "valu": 1228.2, "hbm": 31884117},
-    "fp64/64x8": {"f64": 1128.2, "valu": 1142.1, "hbm": 31875413},
-    "fp64/32x16": {"f64": 1122.8, "valu": 1126.2, "hbm": 31866965},
-    "fp64/32x32": {"f64": 1110.9, "valu": 1113.8, "hbm": 34414050},
-    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1225.9, "hbm": 21814545},
-    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1273.4, "hbm": 21828992},
-    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1216.0, "hbm": 22173562},
-    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1122.3, "hbm": 21814411},
-    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1104.5, "hbm": 21810688},
-    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1049.6, "hbm": 21827712},
+    "fp64/32x8": {"f64": 1237.2, "valu": 1232.1, "hbm": 31879253},
+    "fp64/64x4": {"f64": 1257.8, "valu": 1277.8, "hbm": 31887189},
+    "fp64/16x16": {"f64": 1237.6, "valu": 1225.4, "hbm": 31880021},
+    "fp64/64x8": {"f64": 1128.2, "valu": 1137.6, "hbm": 31866965},
+    "fp64/32x16": {"f64": 1122.8, "valu": 1121.7, "hbm": 31882332},
+    "fp64/32x32": {"f64": 1110.9, "valu": 1109.7, "hbm": 31918734},
+    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1225.9, "hbm": 21814891},
+    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1273.4, "hbm": 21830155},
+    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1216.0, "hbm": 22459670},
+    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1122.3, "hbm": 21813571},
+    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1104.6, "hbm": 21814792},
+    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1049.6, "hbm": 21831680},
 }
 # every VALU instruction of a wave64 occupies a 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second at most

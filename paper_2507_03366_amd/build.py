@@ -22,6 +22,10 @@ HIPCC_FLAGS = [
     # variant (tile shape, face passes, batched) rounds a cell's arithmetic
     # the same way, whatever the surrounding code
     "-ffp-contract=on",
+    # the AMDGPU scheduler's own register-pressure trackers: the FP64 32x32
+    # stage kernel then fits 128 VGPRs without spilling (it spilled two) and
+    # a 512^2 FP64 stage takes 2.4 % less time; other shapes within 1 %
+    "-mllvm", "-amdgpu-use-amdgpu-trackers=1",
     "-Wall", "-Wno-unused-function",
 ]
 
