@@ -131,7 +131,8 @@ typedef struct {
                              give the same bits, SPLIT agrees to rounding */
     int32_t surf_model;   /* 0: F_surf = -C grad mu_c (Sec. 2.4)
                              1: F_surf = -F_l C grad mu_c (Sec. 3.5)     */
-    double dx;            /* cell size                                   */
+    double dx;            /* cell size (along a direction with no width
+                             array, see x_width below)                   */
     double delta_t;       /* streaming step (Sec. 2.5 step 1)            */
     double dt;            /* update step of Eq. (58)                     */
     double rho[3], mu[3], lambda[3], cp[3]; /* [solid, liquid, gas], Eq. (7) */
