@@ -263,3 +263,34 @@ def test_two_phase_neumann_on_a_mesh_refined_at_the_cold_wall(oracle):
     Tex = A.neumann_two_phase_T(X[0], t, k, g["T_b"], g["T_m"], g["T_0"], g["alpha_s"], g["alpha_l"])
     away = (np.abs(X[0] - x_i) > 1.5) & (X[0] < 0.5 * w.sum())
     assert np.abs(T - Tex)[away].max() < 0.01
+
+
+def test_conduction_converges_at_second_order_on_a_smoothly_stretched_mesh(oracle):
+    """Transient conduction from a wall held at 0.5 into liquid at 1 (no phase
+    change) on meshes mapped by x = L (e^{b s} - 1) / (e^b - 1), b = 2 (the last
+    cell 7.4 times the first), against T_w + (T_0 - T_w) erf(x / 2 sqrt(alpha t)):
+    doubling the cells divides the largest error by at least 3 (measured 3.9,
+    and 4.0 for the next doubling).  A cell volume taken from a neighbour, an
+    O(h) relative error, drops it to first order (1.8); swapped half widths
+    move the extrapolation only by O(h^2) on such a mesh and are left to the
+    face-flux pin above."""
+    oracle.set_threads(1)
+    Lx, b, t_end, alpha = 40.0, 2.0, 12.0, 0.4
+    errs = []
+    for n in (40, 80):
+        s = np.arange(n + 1) / n
+        xf = Lx * (np.exp(b * s) - 1.0) / (math.exp(b) - 1.0)
+        w = np.diff(xf)
+        dt = 0.25 * w.min() ** 2 / alpha
+        steps = int(round(t_end / dt))
+        dt = t_end / steps
+        pr = PB.Problem(nx=n, ny=1, x_width=w, delta_t=0.25 * w.min(), dt=dt, lam=(alpha, alpha, alpha),
+                        T_s=0.0, T_l=0.0, latent=1.0, periodic_y=True,
+                        walls={"x-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, 0.5), "x+": PB.Wall(PB.NOSLIP, PB.ADIABATIC)})
+        W, _ = oracle.run(pr, _liquid(pr, np.ones((1, n))), steps)
+        T = oracle.primitives(pr, W)[0][0]
+        x = PB.centres_1d(w)
+        exact = np.array([0.5 + 0.5 * math.erf(xi / (2.0 * math.sqrt(alpha * t_end))) for xi in x])
+        errs.append(np.abs(T - exact).max())
+    assert errs[0] < 0.02
+    assert errs[0] / errs[1] > 3.0, errs
