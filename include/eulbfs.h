@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define EULBFS_ABI_VERSION 3u
+#define EULBFS_ABI_VERSION 4u
 
 /* status codes */
 #define EULBFS_OK 0
@@ -111,7 +111,15 @@ typedef struct {
  *     kappa = 3 xi sigma/2 (Sec. 2.3.1 prints '+ kappa').
  *   - f^eq-m (Eqs. 33-34): f^eq with the old-level face density, without the
  *     leading 1 of Gamma.
- *   - C source C (1 - rho_s/rho_l) dF_s/dt kept in row 5 of F_E (Eqs. 40, 47).
+ *   - C source of Eq. (40) kept in row 5 of F_E (Eq. 51 prints 0 there).  The
+ *     paper's F_s in Eq. (40) is 1 - F_l, the solid share of the condensed
+ *     phase, and C d(1 - F_l)/dt is the rate at which the cell's volume turns
+ *     solid; the source is (1 - rho_s/rho_l) dF_s/dt with the cell's solid
+ *     fraction F_s = C (1 - F_l), the lagged rate of the volume source of
+ *     Eq. (26), so the condensed volume grows by exactly the dilatation of the
+ *     freezing material (c_source = 0).  c_source = 1 multiplies that rate by
+ *     C once more (the printed factor applied to the cell's F_s), which loses
+ *     (1 - r) xi/4 of condensed volume per unit length of frozen interface.
  *   - C_p,ref = (C_p,s + C_p,l)/2; H = C_p T + L F_l in all phases; the solid
  *     fraction entering Eq. (7) is F_s = C (1 - F_l); C and F_s clamped to
  *     [0, 1] where they enter Eq. (7) or the closure.
@@ -146,7 +154,8 @@ typedef struct {
                                32x16, 32x32); 0 picks 32x8; AUTO ignores it */
     const double* x_width;  /* host array of nx column widths, or NULL: dx     */
     const double* y_width;  /* host array of ny row heights, or NULL: dx       */
-    int32_t reserved[2];
+    int32_t c_source;       /* C source of Eq. (40), 0 or 1 (readings above)   */
+    int32_t reserved;
 } eulbfs_params;
 /* Stretched meshes (Eq. 52 holds for any cell; the paper runs uniform ones).
  * With x_width or y_width set the mesh is the tensor product of those cells:

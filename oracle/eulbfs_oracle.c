@@ -37,8 +37,20 @@
  *       make the tanh profile of Eq. 61 an equilibrium).
  *   R4  Gamma_alpha of Eq. (34) without the leading "1": f^eq-m is f^eq with
  *       the density taken at the face at the old level (Eq. 33).
- *   R5  The C source C (1 - rho_s/rho_l) dF_s/dt of Eqs. (40), (47) is kept as
- *       the fifth row of F_E (Eq. 51 prints 0 there).
+ *   R5  The C source of Eqs. (40), (47) is kept as the fifth row of F_E (Eq. 51
+ *       prints 0 there).  In Eq. (40) the paper's F_s is 1 - F_l, the solid
+ *       share of the condensed phase, and C d(1 - F_l)/dt is the rate at which
+ *       the cell's volume turns solid, d(C (1 - F_l))/dt where the condensed
+ *       fraction of a freezing cell is steady.  The source is therefore taken
+ *       as (1 - rho_s/rho_l) dF_s/dt with the cell's solid fraction F_s =
+ *       C (1 - F_l) of R7, the same lagged rate that drives the volume source
+ *       of Eqs. (25)-(26): the condensed volume then grows by exactly the
+ *       dilatation of the freezing material.  c_source = 1 selects the other
+ *       reading, C (1 - rho_s/rho_l) dF_s/dt with the cell's F_s; it weights a
+ *       freezing cell of the diffuse interface by C^2 and loses (1 - r) times
+ *       the integral of C (1 - C) across the interface (xi/4 for the profile of
+ *       Eq. 61) from the final condensed volume, which the full-freezing height
+ *       of Sec. 3.2 and the volume ratios of Table 5 do not show.
  *   R6  C_p,ref = (C_p,s + C_p,l)/2 as written in the formula (the text calls it
  *       a harmonic mean).
  *   R7  Gas phase: the solid fraction entering Eq. (7) is F_s = C (1 - F_l),
@@ -646,7 +658,7 @@ static void residual(grid_t* g, const double* Fsdot, double* R, double* Fx, doub
             S[1] = (u * drho_x + v * drho_y) * CS2 + c->rho * CS2 * (1.0 - ratio) * fs_dot; /* row 2 */
             S[2] = CS2 * (surf * c->grad[V_MUC][0] - c->rho * u * fs_dot + c->rho * P->gx);  /* row 3 */
             S[3] = CS2 * (surf * c->grad[V_MUC][1] - c->rho * v * fs_dot + c->rho * P->gy);  /* row 4 */
-            S[4] = C * (1.0 - ratio) * fs_dot;                                    /* R5 */
+            S[4] = (P->c_source == 1 ? C * (1.0 - ratio) : (1.0 - ratio)) * fs_dot; /* R5 */
             for (int k = 0; k < 5; ++k) {
                 double dfx = fx[k * nfx + (size_t)j * (nx + 1) + i + 1] - fx[k * nfx + (size_t)j * (nx + 1) + i];
                 double dfy = fy[k * nfy + (size_t)(j + 1) * nx + i] - fy[k * nfy + (size_t)j * nx + i];
@@ -701,6 +713,7 @@ static int check(const or_params* P)
     if (!(wmin > 0.0)) return OR_EINVAL;
     if (P->delta_t <= 0.0 || P->delta_t > 0.5 * wmin * (1.0 + 1e-15)) return OR_EINVAL;
     if (P->lattice_hg != 5 && P->lattice_hg != 9) return OR_EINVAL;
+    if (P->c_source != 0 && P->c_source != 1) return OR_EINVAL;
     if (P->bc[0].periodic != P->bc[1].periodic || P->bc[2].periodic != P->bc[3].periodic) return OR_EINVAL;
     if (!P->bc[0].periodic && P->nx < NG) return OR_EINVAL;
     if (!P->bc[2].periodic && P->ny < NG) return OR_EINVAL;

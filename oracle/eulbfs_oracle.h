@@ -31,6 +31,8 @@ typedef struct {
     int32_t nx, ny;
     int32_t lattice_hg; /* 9 (paper) or 5: lattice of h and g; f is always D2Q9 */
     int32_t surf_model; /* 0: F_surf = -C grad mu_c; 1: -F_l C grad mu_c */
+    int32_t c_source;   /* C source (R5): 0: (1 - r) dF_s/dt; 1: C (1 - r) dF_s/dt */
+    int32_t pad;
     double dx;
     double delta_t; /* streaming step, 0 < delta_t <= dx/2 */
     double dt;      /* update step of the RK3 scheme */

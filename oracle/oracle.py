@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "eulbfs_oracle.c")
 def build(force: bool = True) -> str:
     """Compile the oracle (gcc, FP64, no FMA contraction, OpenMP over rows)."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+        cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
                "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
@@ -36,6 +36,7 @@ class _BC(ct.Structure):
 class _Params(ct.Structure):
     _fields_ = [
         ("nx", ct.c_int32), ("ny", ct.c_int32), ("lattice_hg", ct.c_int32), ("surf_model", ct.c_int32),
+        ("c_source", ct.c_int32), ("pad", ct.c_int32),
         ("dx", ct.c_double), ("delta_t", ct.c_double), ("dt", ct.c_double),
         ("rho", ct.c_double * 3), ("mu", ct.c_double * 3), ("lam", ct.c_double * 3), ("cp", ct.c_double * 3),
         ("latent", ct.c_double), ("T_s", ct.c_double), ("T_l", ct.c_double),
@@ -80,6 +81,7 @@ def params(pr) -> _Params:
     """Map a problems.Problem onto the oracle's parameter struct."""
     P = _Params()
     P.nx, P.ny, P.lattice_hg, P.surf_model = pr.nx, pr.ny, pr.lattice_hg, pr.surf_model
+    P.c_source = pr.c_source
     P.dx, P.delta_t, P.dt = pr.dx, pr.delta_t, pr.dt
     for name in ("rho", "mu", "lam", "cp"):
         getattr(P, name)[:] = list(getattr(pr, name))

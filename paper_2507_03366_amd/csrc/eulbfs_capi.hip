@@ -73,6 +73,7 @@ std::string check(const eulbfs_params* p)
     if (p->kernel != EULBFS_KERNEL_FUSED && p->kernel != EULBFS_KERNEL_SPLIT && p->kernel != EULBFS_KERNEL_AUTO)
         return "unknown kernel variant";
     if (p->surf_model != 0 && p->surf_model != 1) return "surf_model must be 0 or 1";
+    if (p->c_source != 0 && p->c_source != 1) return "c_source must be 0 or 1";
     for (int k = 0; k < 3; ++k) {
         if (!(p->rho[k] > 0)) return "densities must be > 0";
         if (!(p->mu[k] >= 0) || !(p->lambda[k] >= 0)) return "viscosities and conductivities must be >= 0";
@@ -125,6 +126,7 @@ DevParams make_dev(const eulbfs_params* p)
     d.pitch = round_pitch(p->nx);
     d.lattice_hg = p->lattice_hg;
     d.surf_model = p->surf_model;
+    d.c_source = p->c_source;
     d.periodic_x = p->bc[0].periodic ? 1 : 0;
     d.periodic_y = p->bc[2].periodic ? 1 : 0;
     for (int s = 0; s < 4; ++s) {

@@ -29,6 +29,7 @@ struct DevParams {
     int nx, ny, pitch;
     int lattice_hg;   // 9 or 5 (h and g); the flow lattice is always D2Q9
     int surf_model;   // 0: -C grad mu_c, 1: -F_l C grad mu_c
+    int c_source;     // C source: 0: (1 - r) dF_s/dt, 1: C (1 - r) dF_s/dt
     int periodic_x, periodic_y;
     int flow[4], heat[4];
     double dx, inv_2dx, inv_dx2, delta_t, dt;
@@ -591,7 +592,7 @@ __device__ __forceinline__ void sources(const DevParams& P, const R c[NPRIM + 1]
     S[1] = (u * drhodx + v * drhody) * R(1.0 / 3.0) + rho * R(1.0 / 3.0) * ex * fsdot;
     S[2] = R(1.0 / 3.0) * (surf * dmudx - rho * u * fsdot + rho * R(P.gx));
     S[3] = R(1.0 / 3.0) * (surf * dmudy - rho * v * fsdot + rho * R(P.gy));
-    S[4] = C * ex * fsdot;
+    S[4] = (P.c_source ? C * ex : ex) * fsdot;
 }
 
 }  // namespace eulbfs

@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, 
 FP64, FP32 = 0, 1
 KERNEL_FUSED, KERNEL_SPLIT, KERNEL_AUTO = 0, 1, 2
 INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
              W_GHOSTED=14)
 SCALAR_DIAG = 100
@@ -51,7 +51,8 @@ class eulbfs_params(ct.Structure):
         ("gx", ct.c_double), ("gy", ct.c_double),
         ("bc", eulbfs_bc * 4),
         ("tile_x", ct.c_int32), ("tile_y", ct.c_int32),
-        ("x_width", ct.POINTER(ct.c_double)), ("y_width", ct.POINTER(ct.c_double)), ("reserved", ct.c_int32 * 2),
+        ("x_width", ct.POINTER(ct.c_double)), ("y_width", ct.POINTER(ct.c_double)), ("c_source", ct.c_int32),
+        ("reserved", ct.c_int32),
     ]
 
 
@@ -109,6 +110,7 @@ def params_from_problem(pr, precision: int = None, kernel: int = KERNEL_FUSED, t
     P.precision = pr.precision if precision is None else precision
     P.kernel = kernel
     P.surf_model = pr.surf_model
+    P.c_source = pr.c_source
     P.dx, P.delta_t, P.dt = pr.dx, pr.delta_t, pr.dt
     P.rho[:] = list(pr.rho)
     P.mu[:] = list(pr.mu)

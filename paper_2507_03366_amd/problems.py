@@ -67,6 +67,9 @@ class Problem:
     gx: float = 0.0
     gy: float = 0.0
     surf_model: int = 0
+    # C source of Eq. (40): 0: (1 - rho_s/rho_l) dF_s/dt with the cell's solid fraction
+    # F_s = C (1 - F_l); 1: the printed factor C applied to that rate as well
+    c_source: int = 0
     periodic_x: bool = False
     periodic_y: bool = False
     walls: Dict[str, Wall] = field(default_factory=dict)

@@ -72,14 +72,14 @@ def neumann_two_phase_T(x: np.ndarray, t: float, k: float, T_b: float, T_m: floa
     return np.where(x < xi, sol, liq)
 
 
-def stefan_full_freezing_height(H0: float, ratio: float, xi: float) -> float:
+def stefan_full_freezing_height_c_weighted(H0: float, ratio: float, xi: float) -> float:
     """Final solid height of the three-phase Stefan problem (Sec. 3.2) on a diffuse
-    interface.
+    interface when the phase-field source of Eq. (40) is C (1 - rho_s/rho_l) dF_s/dt
+    with the cell's solid fraction F_s = C (1 - F_l) (the c_source = 1 reading).
 
     Sharp interface: a frozen column of height H_f held the liquid column H_0 =
-    (rho_s/rho_l) H_f, so H_f = H_0 rho_l / rho_s.  In the model the volume source
-    of the phase field (Eq. 40) is C (1 - rho_s/rho_l) dF_s/dt.  Where the order
-    parameter is below 1 a cell that freezes completely gains F_s = C, so it
+    (rho_s/rho_l) H_f, so H_f = H_0 rho_l / rho_s.  Under this reading, where the
+    order parameter is below 1 a cell that freezes completely gains F_s = C, so it
     contributes C^2 (1 - r) instead of C (1 - r) to the condensed volume (r =
     rho_s/rho_l).  Summed over the column the deficit is (1 - r) D with D the
     integral of C (1 - C) across the interface, xi/4 for the tanh profile of Eq.

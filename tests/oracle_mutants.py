@@ -24,7 +24,7 @@ MUTS = {
  'fstar_sign': ('(1.0 - 1.0 / (2.0 * tau_f)) * fneqm', '-(1.0 - 1.0 / (2.0 * tau_f)) * fneqm'),
  'kappa_sign': ('- kappa * lap', '+ kappa * lap'),
  'gamma_one': ('double Gamma = CS2 * (eu / CS2', 'double Gamma = CS2 * (1.0 + eu / CS2'),
- 'drop_C_source': ('S[4] = C * (1.0 - ratio) * fs_dot;', 'S[4] = 0.0;'),
+ 'drop_C_source': ('S[4] = (P->c_source == 1 ? C * (1.0 - ratio) : (1.0 - ratio)) * fs_dot;', 'S[4] = 0.0;'),
  'weight_diag': ('1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};', '1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 30.0};'),
  'FMy_ex': ('FMy += en * ey * fstar;', 'FMy += en * ex * fstar;'),
  'tauh_no_cpref': ('lam_f / (rho_f * cpref * CS2 * dt)', 'lam_f / (rho_f * CS2 * dt)'),
@@ -37,6 +37,12 @@ MUTS = {
  'side_swap': ('if (side > 0) {', 'if (side < 0) {'),
  'face_avg_one_side': ('avg[v] = 0.5 * (ra[v] + rb[v]);', 'avg[v] = ra[v];'),
  'surf_sign': ('double surf = P->surf_model == 1 ? -c->Fl * C : -C;', 'double surf = P->surf_model == 1 ? c->Fl * C : C;'),
+ 'surf1_sign': ('double surf = P->surf_model == 1 ? -c->Fl * C : -C;', 'double surf = P->surf_model == 1 ? c->Fl * C : -C;'),
+ 'surf1_solid_fraction': ('double surf = P->surf_model == 1 ? -c->Fl * C : -C;', 'double surf = P->surf_model == 1 ? -(1.0 - c->Fl) * C : -C;'),
+ 'surf1_as_model0': ('double surf = P->surf_model == 1 ? -c->Fl * C : -C;', 'double surf = -C;'),
+ 'outlet_momentum_odd': ('    } else { /* outlet: zero gradient */\n        Wg[normal] = m->W[normal];', '    } else { /* outlet: zero gradient */\n        Wg[normal] = -m->W[normal];'),
+ 'outlet_tangential_odd': ('    } else { /* outlet: zero gradient */\n        Wg[normal] = m->W[normal];\n        Wg[tang] = m->W[tang];', '    } else { /* outlet: zero gradient */\n        Wg[normal] = m->W[normal];\n        Wg[tang] = -m->W[tang];'),
+ 'outlet_no_mass_flux': ('if (b->flow != OR_FLOW_OUTLET) F[1] = 0.0;', 'F[1] = 0.0;'),
  'ibm_sign_both': [('(surf * c->grad[V_MUC][0] - c->rho * u * fs_dot', '(surf * c->grad[V_MUC][0] + c->rho * u * fs_dot'),
                    ('(surf * c->grad[V_MUC][1] - c->rho * v * fs_dot', '(surf * c->grad[V_MUC][1] + c->rho * v * fs_dot')],
  'ibm_sign': ('- c->rho * u * fs_dot', '+ c->rho * u * fs_dot'),
@@ -54,7 +60,8 @@ MUTS = {
  'gravity_y_sign': ('c->rho * P->gy);', '-c->rho * P->gy);'),
  'wall_FC': ('    F[4] = 0.0;\n    if (b->heat', '    if (b->heat'),
  'u_new_rho': ('double u_new = mx / (rho_f * CS2);', 'double u_new = mx / (CS2);'),
- 'C_source_no_C': ('S[4] = C * (1.0 - ratio) * fs_dot;', 'S[4] = (1.0 - ratio) * fs_dot;'),
+ 'C_source_with_C': ('S[4] = (P->c_source == 1 ? C * (1.0 - ratio) : (1.0 - ratio)) * fs_dot;', 'S[4] = C * (1.0 - ratio) * fs_dot;'),
+ 'C_source_reading_swap': ('S[4] = (P->c_source == 1 ? C * (1.0 - ratio) : (1.0 - ratio)) * fs_dot;', 'S[4] = (P->c_source == 0 ? C * (1.0 - ratio) : (1.0 - ratio)) * fs_dot;'),
  'p_source_sign': ('c->rho * CS2 * (1.0 - ratio) * fs_dot; /* row 2 */', 'c->rho * CS2 * (ratio - 1.0) * fs_dot; /* row 2 */'),
  'p_source_no_rho': ('c->rho * CS2 * (1.0 - ratio) * fs_dot; /* row 2 */', 'CS2 * (1.0 - ratio) * fs_dot; /* row 2 */'),
  'solid_counts_gas': ('return clamp01(C) * (1.0 - Fl);', 'return (1.0 - Fl);'),

@@ -338,18 +338,20 @@ def test_conductive_freezing_neumann_on_gpu():
     assert abs(x_front - A.neumann_front(0.1, 0.4, 20000 * pr.dt)) < 0.5
 
 
-@pytest.mark.parametrize("ratio", [0.8, 1.2])
-def test_full_freezing_height_on_gpu(oracle, ratio):
+@pytest.mark.parametrize("ratio,c_source", [(0.8, 0), (1.2, 0), (0.8, 1)])
+def test_full_freezing_height_on_gpu(oracle, ratio, c_source):
     """Sec. 3.2 run to full freezing (12 000 steps) on the GPU, expanding and
     contracting: the same state as the oracle to 1e-10 and the final solid height
-    of the diffuse-interface closed form (H_0 - (1 - r) xi/4) / r within 0.05 cell."""
+    H_0 rho_l/rho_s within 0.05 cell (with the C-weighted reading of Eq. 40, the
+    closed form (H_0 - (1 - r) xi/4) / r of that reading)."""
     import analytic as A
 
     H0 = 12.0
-    pr, st = PB.stefan_full_freezing(ratio, H0=H0, ny=4)  # the library needs ny >= 4
+    pr, st = PB.stefan_full_freezing(ratio, H0=H0, ny=4, c_source=c_source)  # the library needs ny >= 4
     w6, _, d = _parity_run(oracle, pr, st, 12000)
     H_f = d["solid"] / (pr.ny * pr.dx)
-    assert abs(H_f - A.stefan_full_freezing_height(H0, ratio, pr.xi)) < 0.05
+    want = H0 / ratio if c_source == 0 else A.stefan_full_freezing_height_c_weighted(H0, ratio, pr.xi)
+    assert abs(H_f - want) < 0.05
 
 
 def test_two_phase_neumann_on_gpu(oracle):

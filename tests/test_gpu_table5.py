@@ -2,12 +2,11 @@
 
 A sessile droplet of each Table 3 fluid (water at rho_s/rho_l = 0.917,
 hexadecane at 1.07, as in Table 5) at contact angles of 120, 135 and 150 deg
-is run on the GPU until its solid volume stops growing.  The condensed volume
-then has to match the Table 5 theoretical ratio rho_l/rho_s up to the
-diffuse-interface term of the C-weighted volume source of Eq. (40): a cell
-with C < 1 adds (1 - r) C^2 instead of (1 - r) C, a deficit of (1 - r) xi/4 per
-unit length of interface (the arc 2 theta R_c of the initial cap).  The same
-configurations on a 100 x 50 grid match the FP64 oracle after 1000 steps.
+is run on the GPU until its solid volume stops growing.  The phase-field source
+of Eq. (40) adds (1 - r) dF_s/dt to the condensed volume (r = rho_s/rho_l), so
+the condensed volume grows by (1 - r) times the solid formed: at full freezing
+it is the Table 5 ratio S_t = rho_l/rho_s.  The same configurations on a
+100 x 50 grid match the FP64 oracle after 1000 steps.
 """
 import math
 import os
@@ -100,7 +99,8 @@ def test_volume_after_full_freezing(fluid, ratio, alpha, key, theta, i):
 
     s = E.Solver(pr, st, kernel=E.KERNEL_AUTO, stream=torch.cuda.Stream())
     try:
-        S0 = s.diagnostics()["volume_C"]
+        d0 = s.diagnostics()
+        S0, solid0 = d0["volume_C"], d0["solid"]
         prev, steps = -1.0, 0
         while steps < 1_000_000:
             s.run(10000)
@@ -115,13 +115,14 @@ def test_volume_after_full_freezing(fluid, ratio, alpha, key, theta, i):
     ratio_n = d["volume_C"] / S0
     S_t = G[f"{key}_S_t"][i]
     assert S_t == pytest.approx(1.0 / ratio, abs=1e-4)
-    # diffuse-interface prediction from the initial cap (radius R_c, arc 2 theta R_c)
-    th = math.radians(theta)
-    Rc = 50.0 * math.sqrt((math.pi / 2.0) / (th - math.sin(th) * math.cos(th)))
-    pred = (1.0 - (1.0 - ratio) * pr.xi / 4.0 * 2.0 * th * Rc / S0) / ratio
-    print(f"{fluid} {theta:.0f} deg: S_n/S_0 = {ratio_n:.5f}, diffuse-interface prediction {pred:.5f}, "
-          f"Table 5 S_t = {S_t}, paper S_n = {G[f'{key}_S_n'][i]}, {steps} steps")
-    assert abs(ratio_n - pred) / pred < 1.5e-3
-    assert abs(ratio_n - S_t) / S_t < 6e-3
-    # every condensed cell away from the interface has frozen
-    assert d["solid"] / d["volume_C"] > 0.98
+    unfrozen = 1.0 - d["solid"] / d["volume_C"]
+    print(f"{fluid} {theta:.0f} deg: S_n/S_0 = {ratio_n:.5f}, Table 5 S_t = {S_t}, paper S_n = "
+          f"{G[f'{key}_S_n'][i]}, error {100 * (ratio_n - S_t) / S_t:+.3f} %, unfrozen condensed fraction "
+          f"{unfrozen:.4f}, {steps} steps")
+    # the condensed volume grew by (1 - r) times the solid formed (the lagged
+    # dF_s/dt telescopes over the steps)
+    assert ratio_n - 1.0 == pytest.approx((1.0 - ratio) * (d["solid"] - solid0) / S0, abs=2e-4)
+    # within the paper's largest Table 5 error once the part of the diffuse
+    # interface that has not frozen yet is accounted for
+    assert abs(ratio_n - S_t) / S_t < 6.4e-4 + abs(1.0 - ratio) * unfrozen
+    assert unfrozen < 0.02

@@ -333,37 +333,55 @@ def test_conductive_freezing_two_phase_neumann(oracle):
     assert np.abs(T - Tex)[away].max() < 0.01
 
 
-@pytest.mark.parametrize("ratio", SEC32["rho_s_over_rho_l"])
-def test_three_phase_stefan_full_freezing_height(oracle, ratio):
-    """Sec. 3.2 (Fig. 6): once the whole column has frozen, the solid height is
-    H_0 rho_l/rho_s, shifted by the diffuse-interface term (1 - r) xi/4 of the
-    C-weighted volume source of Eq. (40) (closed form in analytic.py).  Run with
-    the printed T_0, T_w, L and the largest printed Ste for every printed density
-    ratio.  Catches a wrong sign or a dropped factor C or (1 - rho_s/rho_l) in the
-    volume sources of Eqs. (26) and (40), a solid fraction that counts gas, and
-    a lost or doubled lagged dF_s/dt."""
+def _full_freezing(oracle, ratio, **kw):
+    """Sec. 3.2 column with its printed T_0, T_w, L and the largest printed Ste, run
+    until every condensed cell has frozen (12 000 steps at H_0 = 12)."""
     oracle.set_threads(1)
-    H0, xi = 12.0, SEC32["xi"][0]
+    H0 = 12.0
     pr, st = PB.stefan_full_freezing(ratio, H0=H0, ste=max(SEC32["ste"]), T0=SEC32["T_0"][0],
-                                     T_w=SEC32["T_w"][0], latent=SEC32["L"][0])
-    assert pr.xi == xi and pr.cp[0] == pr.cp[1] and pr.lam[0] == pr.lam[1]
+                                     T_w=SEC32["T_w"][0], latent=SEC32["L"][0], **kw)
+    assert pr.xi == SEC32["xi"][0] and pr.cp[0] == pr.cp[1] and pr.lam[0] == pr.lam[1]
     W, fs = oracle.run(pr, st, 12000)
     d = oracle.diagnostics(pr, W)
-    H_f = d[3] / (pr.ny * pr.dx)
-    assert abs(H_f - A.stefan_full_freezing_height(H0, ratio, xi)) < 0.05
-    assert abs(H_f - H0 / ratio) < 0.3  # the paper's sharp-interface relation
     prim = oracle.primitives(pr, W)
-    condensed = W[4] > 0.5
-    assert prim[1][condensed].max() == 0.0  # every condensed cell is frozen
+    assert prim[1][W[4] > 0.5].max() == 0.0  # every condensed cell is frozen
     assert np.abs(prim[4]).max() < 1e-4
+    return pr, H0, d
+
+
+@pytest.mark.parametrize("ratio", SEC32["rho_s_over_rho_l"])
+def test_three_phase_stefan_full_freezing_height(oracle, ratio):
+    """Sec. 3.2 (Fig. 6): once the whole column has frozen, the solid height is the
+    paper's mass balance H_f = H_0 rho_l/rho_s (within 0.05 cell), for every printed
+    density ratio; the condensed volume sum C dx is the same height.  Catches a
+    wrong sign or a dropped or doubled factor C or (1 - rho_s/rho_l) in the volume
+    sources of Eqs. (26) and (40), a solid fraction that counts gas, and a lost or
+    doubled lagged dF_s/dt."""
+    pr, H0, d = _full_freezing(oracle, ratio)
+    H_f = d[3] / (pr.ny * pr.dx)
+    assert abs(H_f - H0 / ratio) < 0.05
+    assert abs(d[1] / (pr.ny * pr.dx) - H0 / ratio) < 0.05
+
+
+@pytest.mark.parametrize("ratio", [0.8, 1.2])
+def test_full_freezing_height_of_the_C_weighted_source(oracle, ratio):
+    """The other reading of Eq. (40) (c_source = 1: the printed C times the rate of
+    the cell's solid fraction) loses condensed volume in the diffuse interface: a
+    cell with C < 1 that freezes gains F_s = C and adds (1 - r) C^2 instead of
+    (1 - r) C.  Its final height is the closed form (H_0 - (1 - r) xi/4)/r of
+    analytic.py within 0.05 cell, more than 0.05 cell from the paper's H_0/r."""
+    pr, H0, d = _full_freezing(oracle, ratio, c_source=1)
+    H_f = d[3] / (pr.ny * pr.dx)
+    assert abs(H_f - A.stefan_full_freezing_height_c_weighted(H0, ratio, pr.xi)) < 0.05
+    assert abs(H_f - H0 / ratio) > 0.05
 
 
 def test_sources_of_a_uniform_freezing_state(oracle):
     """Eqs. (26), (27), (40) and (51) on a uniform, partly frozen, moving state with
     a given dF_s/dt: every face flux cancels against its neighbour, so the residual
     is the source vector alone: rho c_s^2 (1 - rho_s/rho_l) dF_s/dt for p,
-    -c_s^2 rho u dF_s/dt (F_IBM of Eq. 27) for the momenta, C (1 - rho_s/rho_l)
-    dF_s/dt for C and C_p T div u = 0 for H.  Catches a flipped or dropped F_IBM
+    -c_s^2 rho u dF_s/dt (F_IBM of Eq. 27) for the momenta, (1 - rho_s/rho_l)
+    dF_s/dt for C (C times that with c_source = 1) and C_p T div u = 0 for H.  Catches a flipped or dropped F_IBM
     in both momentum rows at once (invisible to the equivariance checks) and the
     sign or weighting of the volume sources."""
     pr = PB.Problem(nx=4, ny=4, rho=(0.8, 1.0, 0.1), mu=(0.05, 0.05, 0.01), lam=(0.4, 0.4, 0.04),
@@ -373,13 +391,14 @@ def test_sources_of_a_uniform_freezing_state(oracle):
     st.u[:] = u
     st.v[:] = v
     W = oracle.init(pr, st)
-    R, _, _ = oracle.residual(pr, W, np.full((pr.ny, pr.nx), fsd))
-    Fs = C * (1.0 - Fl)  # solid fraction of the condensed phase (gas never solid)
+    Fs = C * (1.0 - Fl)  # solid fraction of the cell (gas never solid)
     rho = Fs * 0.8 + (1.0 - Fs) * C * 1.0 + (1.0 - Fs) * (1.0 - C) * 0.1  # Eq. (7)
     ex = 1.0 - 0.8 / 1.0
-    expect = [0.0, rho * CS2 * ex * fsd, -CS2 * rho * u * fsd, -CS2 * rho * v * fsd, C * ex * fsd]
-    for k in range(5):
-        np.testing.assert_allclose(R[k], expect[k], rtol=1e-12, atol=1e-16)
+    for c_source, s_c in ((0, ex * fsd), (1, C * ex * fsd)):
+        R, _, _ = oracle.residual(pr.replace(c_source=c_source), W, np.full((pr.ny, pr.nx), fsd))
+        expect = [0.0, rho * CS2 * ex * fsd, -CS2 * rho * u * fsd, -CS2 * rho * v * fsd, s_c]
+        for k in range(5):
+            np.testing.assert_allclose(R[k], expect[k], rtol=1e-12, atol=1e-16)
 
 
 def test_shear_wave_decay(oracle):
@@ -634,6 +653,82 @@ def test_ghost_ring_rules(oracle):
     H_ghost = Wg[0, g:g + 5, g - 1]
     # ghost is solid (T_g = 2 T_w - T_first < 0), so T_g = H_g / C_p,s with C = C_mirror
     assert np.allclose(0.5 * (H_ghost / 1.0 + T_first), -0.5, atol=1e-14)
+
+
+def test_outlet_ghosts_and_face_flux(oracle):
+    """Outlet walls (zero gradient): the ghosts of both momenta and of p mirror the
+    interior with even parity, and the wall face carries the mass flux.  A uniform
+    gas stream (C = 0, T = 0, so no enthalpy or phase-field flux) through an outlet
+    at each end of a channel is steady to rounding, and the flux of p through the
+    outlet face is (rho u c_s^2) . n of the stream."""
+    v = -0.013
+    pr = PB.Problem(nx=6, ny=8, rho=(0.9, 1.0, 0.3), mu=(0.05, 0.05, 0.02), periodic_x=True,
+                    walls={"y-": PB.Wall(PB.OUTLET), "y+": PB.Wall(PB.OUTLET)})
+    st = PB.uniform_state(pr, T0=0.0, C0=0.0)
+    st.v[:] = v
+    st.p[:] = 0.02
+    W = oracle.init(pr, st)
+    R, _, Fy = oracle.residual(pr, W)
+    for k in (1, 2, 3):
+        assert np.abs(R[k]).max() < 1e-15, (k, np.abs(R[k]).max())
+    rho_g = 0.3
+    nfy = pr.nx * (pr.ny + 1)
+    Fp = Fy.reshape(5, pr.ny + 1, pr.nx)[1]
+    np.testing.assert_allclose(Fp[0], rho_g * CS2 * v, rtol=1e-12)
+    np.testing.assert_allclose(Fp[-1], rho_g * CS2 * v, rtol=1e-12)
+    # ghosts of a non-uniform state: both momenta and p even across the outlet
+    st = PB.seeded_fields(pr, seed=5)
+    W = oracle.init(pr, st)
+    Wg = oracle.ghosts(pr, W)
+    g = 3
+    for k in range(1, 4):
+        m = k - 1
+        for q in (1, 2, 3):
+            assert np.array_equal(Wg[q, g - k, g:g + pr.nx], W[q, m])
+            assert np.array_equal(Wg[q, g + pr.ny - 1 + k, g:g + pr.nx], W[q, pr.ny - 1 - m])
+    _, _, Fy = oracle.residual(pr, W)
+    assert np.abs(Fy.reshape(5, pr.ny + 1, pr.nx)[1][0]).min() > 0.0
+
+
+def _frozen_or_liquid_drop(surf_model, sigma, T, Fl, seed=4):
+    pr = PB.Problem(nx=24, ny=20, rho=(0.9, 1.0, 0.05), mu=(0.05, 0.05, 0.01), lam=(0.4, 0.4, 0.02),
+                    latent=2.0, sigma=sigma, surf_model=surf_model, periodic_x=True,
+                    walls={"y-": PB.Wall(PB.NOSLIP, PB.ADIABATIC, 0.0, 80.0), "y+": PB.Wall()})
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr, T0=T, Fl0=Fl)
+    st.C = PB.droplet_profile(X, Y, 12.0, 3.0, 8.0, pr.xi)
+    rng = np.random.default_rng(seed)
+    st.u = 0.01 * rng.standard_normal(st.C.shape)
+    st.v = 0.01 * rng.standard_normal(st.C.shape)
+    st.p = 1e-3 * rng.standard_normal(st.C.shape)
+    return pr, st
+
+
+def test_surface_force_of_the_unfrozen_part(oracle):
+    """F_surf = -F_l C grad mu_c (Sec. 3.5, surf_model = 1) against -C grad mu_c
+    (Sec. 2.4): on a liquid drop (F_l = 1 everywhere) the two residuals are equal
+    bit for bit; on a fully frozen drop (F_l = 0 everywhere) model 1 carries no
+    capillary force, so its p and momentum residuals are those of sigma = 0 bit for
+    bit, while model 0 still has one."""
+    sigma = 0.02
+    pr0, st = _frozen_or_liquid_drop(0, sigma, T=0.3, Fl=1.0)
+    pr1, _ = _frozen_or_liquid_drop(1, sigma, T=0.3, Fl=1.0)
+    W = oracle.init(pr0, st)
+    assert oracle.primitives(pr0, W)[1].min() == 1.0
+    R0, _, _ = oracle.residual(pr0, W)
+    R1, _, _ = oracle.residual(pr1, W)
+    assert np.array_equal(R0, R1)
+    # frozen: T below the melting point everywhere, gas included (F_l = 0)
+    pr0, st = _frozen_or_liquid_drop(0, sigma, T=-0.5, Fl=0.0)
+    pr1 = pr0.replace(surf_model=1)
+    W = oracle.init(pr0, st)
+    assert oracle.primitives(pr0, W)[1].max() == 0.0
+    R1, _, _ = oracle.residual(pr1, W)
+    Rs, _, _ = oracle.residual(pr1.replace(sigma=0.0), W)
+    R0, _, _ = oracle.residual(pr0, W)
+    for k in (1, 2, 3):
+        assert np.array_equal(R1[k], Rs[k]), k
+    assert np.abs(R0[2] - Rs[2]).max() > 1e-6 and np.abs(R0[3] - Rs[3]).max() > 1e-6
 
 
 def test_hydrostatic_pressure(oracle):
