@@ -253,6 +253,20 @@ int eulbfs_set_field(eulbfs_t h, int32_t what, const void* in, size_t bytes, int
  * created with EULBFS_KERNEL_SPLIT, whose workspace holds it.  Synchronises. */
 int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): eulbfs_residual with
+ * its device scratch (split-kernel planes, residual planes, staging) in a
+ * static array of EULBFS_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends, instead of a temporary
+ * allocation.  Same arguments, outputs and synchronisation as eulbfs_residual;
+ * calls no hipMalloc or hipFree.  The solver's device must be current.
+ * EULBFS_EINVAL when the grid needs more scratch than the array holds (square
+ * grids up to 495 x 495 cells in FP64, 634 x 634 in FP32).  Every call on one device shares that device's
+ * array (nothing in it has to start at zero; it keeps the last call's
+ * contents): calls that overlap on one device race. */
+#define EULBFS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int eulbfs_residual_noalloc(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device);
+
 /* Release a solver; NULL is accepted. */
 int eulbfs_destroy(eulbfs_t h);
 

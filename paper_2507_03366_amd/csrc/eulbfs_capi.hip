@@ -42,6 +42,33 @@ int set_err(std::string* where, int code, const std::string& msg)
 
 bool stretched(const eulbfs_params* p) { return p->x_width != nullptr || p->y_width != nullptr; }
 
+// Scratch of eulbfs_residual_noalloc: one array on every device the library
+// runs on, held until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, not a device address: host code only ever uses the
+// per-device address that hipGetSymbolAddress returns (noalloc_scratch).
+static __device__ __align__(256) char scratch[EULBFS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev (which must be current), looked up
+// once per device.
+int noalloc_scratch(int dev, char** out, std::string* err)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return set_err(err, EULBFS_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_err(err, EULBFS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return EULBFS_OK;
+}
+
 // Smallest of n widths (dx for a NULL array); 0 if one is not finite and > 0.
 double min_width(const double* w, double dx, int n)
 {
@@ -385,6 +412,7 @@ struct eulbfs_solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_failed = false;
+    int device = -1;  // device current at create
 };
 
 namespace {
@@ -557,20 +585,30 @@ int do_set_field(eulbfs_solver* h, int what, const void* in, size_t bytes, int o
     return EULBFS_OK;
 }
 
+// Device scratch of one residual evaluation: the split scratch (unless the
+// workspace holds one), the residual planes in the state's pitch layout and a
+// dense double staging area for the copies out.
 template <typename R>
-int do_residual(eulbfs_solver* h, double* Rout, double* Fx, double* Fy, int on_dev)
+size_t residual_scratch_bytes(const eulbfs_solver* h)
+{
+    const Layout& L = h->L;
+    const size_t sb = L.split ? 0 : align_up(split_scratch_bytes(L, sizeof(R)));
+    return sb + 5 * L.plane_R + align_up((size_t)5 * (h->prm.nx + 1) * (h->prm.ny + 1) * 8);
+}
+
+// ext: caller-provided scratch of residual_scratch_bytes<R>(h) bytes, or NULL
+// to allocate it here (and free it before returning).
+template <typename R>
+int do_residual(eulbfs_solver* h, double* Rout, double* Fx, double* Fy, int on_dev, char* ext)
 {
     std::string* err = &h->err;
     const Layout& L = h->L;
     const int nx = h->prm.nx, ny = h->prm.ny;
     const size_t rs = sizeof(R);
-    // split scratch (unless the workspace holds one), residual planes in the
-    // state's pitch layout, dense double staging for the copies out
     const size_t sb = L.split ? 0 : align_up(split_scratch_bytes(L, rs));
     const size_t rbytes = 5 * L.plane_R;
-    const size_t dense = align_up((size_t)5 * (nx + 1) * (ny + 1) * 8);
-    char* tmp = nullptr;
-    HIP_TRY(hipMalloc(&tmp, sb + rbytes + dense));
+    char* tmp = ext;
+    if (!ext) HIP_TRY(hipMalloc(&tmp, residual_scratch_bytes<R>(h)));
     SplitScratch<R> X;
     if (L.split) {
         X = split_at<R>(h->ws, L);
@@ -608,8 +646,10 @@ int do_residual(eulbfs_solver* h, double* Rout, double* Fx, double* Fy, int on_d
         if (e == hipSuccess) e = hipMemcpyAsync(Fy, dd, (size_t)5 * nx * (ny + 1) * 8, kind, h->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    const hipError_t ef = hipFree(tmp);
-    if (e == hipSuccess) e = ef;
+    if (!ext) {
+        const hipError_t ef = hipFree(tmp);
+        if (e == hipSuccess) e = ef;
+    }
     if (e != hipSuccess) return set_err(err, EULBFS_EDEVICE, std::string("residual: ") + hipGetErrorString(e));
     return EULBFS_OK;
 }
@@ -761,6 +801,7 @@ int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
     h->L = L;
     h->stream = (hipStream_t)hip_stream;
     h->tile = tile_of(prm);
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
     if (d_ws) {
         h->ws = (char*)d_ws;
     } else {
@@ -883,8 +924,27 @@ int eulbfs_set_field(eulbfs_t h, int32_t what, const void* in, size_t bytes, int
 int eulbfs_residual(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device)
 {
     if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
-    return h->prm.precision == EULBFS_FP32 ? do_residual<float>(h, R, Fx, Fy, on_device)
-                                           : do_residual<double>(h, R, Fx, Fy, on_device);
+    return h->prm.precision == EULBFS_FP32 ? do_residual<float>(h, R, Fx, Fy, on_device, nullptr)
+                                           : do_residual<double>(h, R, Fx, Fy, on_device, nullptr);
+}
+
+int eulbfs_residual_noalloc(eulbfs_t h, double* R, double* Fx, double* Fy, int32_t on_device)
+{
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    const size_t need = h->prm.precision == EULBFS_FP32 ? residual_scratch_bytes<float>(h)
+                                                        : residual_scratch_bytes<double>(h);
+    if (need > EULBFS_NOALLOC_SCRATCH_BYTES)
+        return set_err(&h->err, EULBFS_EINVAL,
+                       "residual_noalloc: the grid needs " + std::to_string(need) +
+                           " bytes of scratch, more than the static " +
+                           std::to_string((size_t)EULBFS_NOALLOC_SCRATCH_BYTES));
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+        return set_err(&h->err, EULBFS_EINVAL, "residual_noalloc: the solver's device must be current");
+    char* scr = nullptr;
+    if (int rc = noalloc_scratch(dev, &scr, &h->err)) return rc;
+    return h->prm.precision == EULBFS_FP32 ? do_residual<float>(h, R, Fx, Fy, on_device, scr)
+                                           : do_residual<double>(h, R, Fx, Fy, on_device, scr);
 }
 
 int eulbfs_destroy(eulbfs_t h)

@@ -81,12 +81,13 @@ def lib():
         L.eulbfs_query.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
         L.eulbfs_set_field.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
         L.eulbfs_residual.argtypes = [vp, dp, dp, dp, ct.c_int32]
+        L.eulbfs_residual_noalloc.argtypes = [vp, dp, dp, dp, ct.c_int32]
         L.eulbfs_destroy.argtypes = [vp]
         L.eulbfs_schedule.argtypes = [vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.eulbfs_last_error.argtypes = [vp]
         L.eulbfs_last_error.restype = ct.c_char_p
         for f in ("eulbfs_check_params", "eulbfs_create", "eulbfs_step", "eulbfs_run", "eulbfs_query",
-                  "eulbfs_set_field", "eulbfs_residual", "eulbfs_destroy"):
+                  "eulbfs_set_field", "eulbfs_residual", "eulbfs_residual_noalloc", "eulbfs_destroy"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -209,6 +210,16 @@ def eulbfs_residual(h, nx: int, ny: int):
     Fy = np.zeros((5, ny + 1, nx))
     dp = ct.POINTER(ct.c_double)
     _raise(lib().eulbfs_residual(h, R.ctypes.data_as(dp), Fx.ctypes.data_as(dp), Fy.ctypes.data_as(dp), 0), h)
+    return R, Fx, Fy
+
+
+def eulbfs_residual_noalloc(h, nx: int, ny: int):
+    R = np.zeros((5, ny, nx))
+    Fx = np.zeros((5, ny, nx + 1))
+    Fy = np.zeros((5, ny + 1, nx))
+    dp = ct.POINTER(ct.c_double)
+    _raise(lib().eulbfs_residual_noalloc(h, R.ctypes.data_as(dp), Fx.ctypes.data_as(dp), Fy.ctypes.data_as(dp), 0),
+           h)
     return R, Fx, Fy
 
 
