@@ -131,15 +131,24 @@ def workload(name: str):
     return pr, st, desc
 
 
-def cpu_baseline(pr, st, budget_s: float):
-    """Time the FP64 oracle as it stands on this host's cores."""
-    from oracle import oracle as O
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    O.build(force=False)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    O.set_threads(threads)
+
+def oracle_rate(pr, st, budget_s: float, threads: int):
+    """Oracle steps of the workload from its initial state for about budget_s
+    seconds on `threads` threads: (MLUPS, steps, seconds)."""
+    from oracle import oracle as O
     import numpy as np
 
+    O.set_threads(threads)
     W = O.init(pr, st)
     fs = np.zeros((pr.ny, pr.nx))
     t0 = time.perf_counter()
@@ -151,9 +160,90 @@ def cpu_baseline(pr, st, budget_s: float):
         W, fs = O.step(pr, W, fs, more)
         steps += more
     el = time.perf_counter() - t0
-    return {"value": pr.cells * steps / el / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+    return pr.cells * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(pr, st, budget_s: float):
+    """Time the FP64 oracle as it stands (gcc -O3, OpenMP over rows) on this
+    host's cores, and on one thread."""
+    from oracle import oracle as O
+
+    O.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    mlups, steps, el = oracle_rate(pr, st, budget_s, threads)
+    used = O.num_threads()
+    one, steps1, el1 = oracle_rate(pr, st, budget_s / 3.0, 1)
+    O.set_threads(threads)
+    return {"value": mlups, "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{steps} oracle steps of the same {pr.nx}x{pr.ny} workload from its initial state, "
-                      f"{el:.1f} s wall"}
+                      f"{el:.1f} s wall on {used} threads",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "one_thread": {"value": one, "unit": "MLUPS", "sample": f"{steps1} steps, {el1:.1f} s wall"}}
+
+
+def hbm_point(name: str, precision: int, steps: int):
+    """A single large grid: MLUPS and compulsory HBM bytes per second of the
+    autotuned fused kernel (HIP events on the solver's stream)."""
+    import torch
+    from paper_2507_03366_amd import eulbfs as E
+
+    pr, st, _ = workload(name)
+    stream = torch.cuda.Stream()
+    s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream)
+    try:
+        sched = s.schedule()
+        s.step(8)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        finite = s.diagnostics()["nonfinite"] == 0
+    finally:
+        s.close()
+    bpcs = bytes_per_cell_step(precision)
+    rate = pr.cells * steps / (ms * 1e-3)
+    ws = pr.cells * (bpcs / 44.0 * 16)  # W^n, two RK registers and dF_s/dt, bytes
+    return {"workload": f"{pr.nx}x{pr.ny}", "precision": "fp64" if precision == 0 else "fp32",
+            "tile": f"{sched[1]}x{sched[2]}", "steps": steps, "ms_per_step": round(ms / steps, 5),
+            "mlups": round(rate / 1e6, 1), "bytes_per_cell_step": bpcs,
+            "gbs": round(rate * bpcs / 1e9, 1), "frac": round(rate * bpcs / 1e9 / HBM_PEAK_GBS, 4),
+            "working_set_mb": round(ws / 1e6, 1), "finite": bool(finite)}
+
+
+def hbm_batch_point(count: int, n: int, steps: int):
+    """count droplets of n x n in one FP32 batch, advanced by ticks of `steps`
+    steps: MLUPS and compulsory HBM bytes per second of the batched kernel."""
+    import torch
+    from paper_2507_03366_amd import eulbfs as E
+    from paper_2507_03366_amd import problems as PB
+
+    pr, st = PB.static_droplet(n=n, R=n / 4)
+    pr = pr.replace(sigma=PB.static_droplet()[0].sigma, precision=1)
+    need = E.eulbfs_batch_request_bytes(E.params_from_problem(pr, precision=E.FP32))
+    stream = torch.cuda.Stream()
+    b = E.Batch(need * count + (64 << 20), count, precision=E.FP32, stream=stream)
+    try:
+        for _ in range(count):
+            assert b.admit(pr, st, 2 * steps + 8) is not None
+        b.tick(8)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.tick(steps)
+        b.tick(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+    finally:
+        b.close()
+    bpcs = bytes_per_cell_step(1)
+    rate = count * pr.cells * 2 * steps / (ms * 1e-3)
+    return {"workload": f"{count} x {n}x{n} batch", "precision": "fp32", "tile": "32x16", "steps": 2 * steps,
+            "ms_per_step": round(ms / (2 * steps), 5), "mlups": round(rate / 1e6, 1), "bytes_per_cell_step": bpcs,
+            "gbs": round(rate * bpcs / 1e9, 1), "frac": round(rate * bpcs / 1e9 / HBM_PEAK_GBS, 4),
+            "working_set_mb": round(count * need / 1e6, 1)}
 
 
 def main():
@@ -171,6 +261,8 @@ def main():
     ap.add_argument("--serving", type=int, default=256, metavar="REQUESTS",
                     help="requests of the continuous-batching serving mix (0: skip)")
     ap.add_argument("--serving-steps", type=int, default=2000)
+    ap.add_argument("--no-hbm-sweep", action="store_true",
+                    help="skip the large-grid points whose working set exceeds the 256 MB Infinity Cache")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -282,10 +374,15 @@ def main():
                           "what": "create from host planes + the timed steps + W read back to the host"},
         "diagnostics_after": {k: float(v) for k, v in diag.items()},
     }
+    if not args.no_hbm_sweep:
+        # the 512 x 512 state (34 MB) lives in the 256 MB Infinity Cache: the
+        # HBM fraction is measured on working sets well beyond it
+        out["hbm_sweep"] = [hbm_point("R4096", 0, 60), hbm_point("R4096", 1, 60), hbm_batch_point(64, 512, 30)]
     if args.serving:
         from paper_2507_03366_amd import serve as S
 
-        out["serving"] = S.run_mix(count=args.serving, nsteps=args.serving_steps)
+        out["serving"] = S.run_mix(count=args.serving, nsteps=args.serving_steps,
+                                   accuracy_requests=min(24, args.serving))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, st, args.cpu_budget)
     print(json.dumps(out), flush=True)

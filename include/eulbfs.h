@@ -43,14 +43,14 @@
 extern "C" {
 #endif
 
-#define EULBFS_ABI_VERSION 4u
+#define EULBFS_ABI_VERSION 5u
 
 /* status codes */
 #define EULBFS_OK 0
 #define EULBFS_EINVAL (-1)    /* bad argument or parameter                        */
 #define EULBFS_ENOMEM (-2)    /* workspace too small or allocation failed         */
 #define EULBFS_EDEVICE (-3)   /* a HIP call failed                                */
-#define EULBFS_EUNSTABLE (-4) /* NaN/Inf or a speed above c_s; handle poisoned    */
+#define EULBFS_EUNSTABLE (-4) /* NaN/Inf, speed above c_s or C out of range; poisoned */
 #define EULBFS_EBUSY (-5)     /* no free slot / HBM budget (batch API)            */
 #define EULBFS_ENOTSUP (-6)   /* valid request this build does not provide        */
 
@@ -208,13 +208,35 @@ typedef struct {
 #define EULBFS_FIELD_W_GHOSTED 14 /* 5 planes of (nx+6)*(ny+6): state with its ghost ring */
 /* Scalars: EULBFS_SCALAR_DIAG fills EULBFS_NDIAG doubles:
  *   [0] sum rho dV, [1] sum C dV, [2] sum H dV, [3] sum F_s dV, [4] max |u|,
- *   [5] non-finite cell count, [6] sum_j F_s(nx/2, j) dx (tip height on the
- *   middle column), [7] time, [8] steps taken, [9] dt
- * The sums are FP64 and deterministic (fixed two-pass order, no atomics). */
+ *   [5] non-finite cell count, [6] sum_j F_s(nx/2, j) dy (tip height on the
+ *   middle column), [7] time, [8] steps taken, [9] dt, [10] min C,
+ *   [11] max C, [12] sum_i clamp(C(i, 0)) dx (wetted length on the y- wall:
+ *   the spreading diameter D of Sec. 3.5 for a drop on that wall, D/D_0 its
+ *   spreading factor), [13] sum_j clamp(C(nx/2, j)) dy (height of the
+ *   condensed phase on the middle column: the apex or bounce height H_b of
+ *   Sec. 3.5, Table 7, for a drop centred there)
+ * Widths replace dx and dy on a stretched mesh.  The sums are FP64 and
+ * deterministic (fixed two-pass order, no atomics). */
 #define EULBFS_SCALAR_DIAG 100
-#define EULBFS_NDIAG 10
+#define EULBFS_NDIAG 14
+/* Watchdog (eulbfs_run, eulbfs_query, eulbfs_batch_query of the integrals): the
+ * state is unstable when a cell is non-finite, a speed exceeds the lattice
+ * sound speed c_s = 1/sqrt(3), or the order parameter leaves [-EULBFS_C_MARGIN,
+ * 1 + EULBFS_C_MARGIN] (F_s = clamp(C)(1 - F_l) itself is in [0, 1] by
+ * construction). */
+#define EULBFS_C_MARGIN 0.5
 
-/* Host-only: validate parameters.  msg (may be NULL) receives the reason. */
+/* Host-only: validate parameters.  msg (may be NULL) receives the reason.
+ * Besides the ranges stated above: xi must span two cells (2 dx, the smallest
+ * width on a stretched mesh), and dt must lie within the stability bounds of
+ * the explicit SSP-RK3 step (-2.51 on the real axis, sqrt(3) on the imaginary
+ * one) for the diffusive processes on the actual mesh: heat (largest lambda /
+ * (rho C_p) of the phases), momentum (2 mu / rho + c_s^2 delta_t, the
+ * compressive viscous mode of the flux), the Cahn-Hilliard operator
+ * M_c (kappa l^2 + 2 beta l) and the acoustic mode c_s dt (1/dx + 1/dy), with
+ * l the largest eigenvalue of the compact finite-volume Laplacian on the mesh
+ * (wall cells stiffer where the value is held: Dirichlet temperature, no-slip
+ * momentum). */
 int eulbfs_check_params(const eulbfs_params* prm, char* msg, size_t msg_len);
 
 /* Host-only: bytes of device workspace a solver with these parameters needs
@@ -231,14 +253,20 @@ typedef struct eulbfs_solver* eulbfs_t;
 /* Enqueue nsteps SSP-RK3 steps (Eq. 58); asynchronous. */
 int eulbfs_step(eulbfs_t h, int64_t nsteps);
 
-/* eulbfs_step, then synchronise the stream and check the state: returns
- * EULBFS_EUNSTABLE (and poisons the handle) if any cell is non-finite or any
- * speed |u| exceeds the lattice sound speed c_s = 1/sqrt(3) (the flux
- * reconstruction assumes low Mach number). */
-int eulbfs_run(eulbfs_t h, int64_t nsteps);
+/* eulbfs_step of min(nsteps, the steps that bring the time to t_end) (the
+ * fixed dt reaches t_end after ceil((t_end - t)/dt) steps; t_end = INFINITY
+ * for nsteps alone; NaN is EULBFS_EINVAL), then synchronise the stream and
+ * run the watchdog: EULBFS_EUNSTABLE (and a poisoned handle) if a cell is
+ * non-finite, a speed |u| exceeds the lattice sound speed c_s = 1/sqrt(3)
+ * (the flux reconstruction assumes low Mach number) or C leaves its range
+ * (EULBFS_C_MARGIN). */
+int eulbfs_run(eulbfs_t h, int64_t nsteps, double t_end);
 
 /* Read a field (EULBFS_FIELD_*) or the diagnostics (EULBFS_SCALAR_DIAG) into
- * out (bytes large enough; host memory unless out_on_device).  Synchronises. */
+ * out (bytes large enough; host memory unless out_on_device).  Synchronises.
+ * The diagnostics go through the watchdog of eulbfs_run; on an unstable state,
+ * or a handle poisoned before, the output is still written and the call
+ * returns EULBFS_EUNSTABLE. */
 int eulbfs_query(eulbfs_t h, int32_t what, void* out, size_t bytes, int32_t out_on_device);
 
 /* Overwrite one conserved plane (FIELD_H..FIELD_FSDOT) or all six

@@ -81,6 +81,111 @@ double min_width(const double* w, double dx, int n)
     return m;
 }
 
+// Largest eigenvalue of the compact diffusion operator along one direction
+// for a unit diffusivity: the finite-volume Laplacian over cells of widths w
+// (NULL: n cells of dx) with the distance between neighbouring centres the
+// mean of their widths, and at each wall either a mirrored ghost (zero flux)
+// or an odd one (a held value at the wall: Dirichlet temperature, no-slip
+// momentum).  Its symmetric tridiagonal form is bisected with Sturm counts; a
+// periodic direction takes the Gershgorin bound (exact for a uniform mesh of
+// even n).
+double diffusion_radius(const double* w, double dx, int n, bool periodic, bool odd_lo, bool odd_hi)
+{
+    auto W = [&](int i) { return w ? w[i] : dx; };
+    std::vector<double> a(n, 0.0), b(n, 0.0);  // b[i] couples cells i and i + 1 (mod n)
+    for (int i = 0; i < n; ++i) {
+        if (i > 0 || periodic) {
+            const int j = (i + n - 1) % n;
+            a[i] += 1.0 / (W(i) * 0.5 * (W(i) + W(j)));
+        } else if (odd_lo) {
+            a[i] += 2.0 / (W(i) * W(i));
+        }
+        if (i < n - 1 || periodic) {
+            const int j = (i + 1) % n;
+            const double h = 0.5 * (W(i) + W(j));
+            a[i] += 1.0 / (W(i) * h);
+            b[i] = 1.0 / (h * std::sqrt(W(i) * W(j)));
+        } else if (odd_hi) {
+            a[i] += 2.0 / (W(i) * W(i));
+        }
+    }
+    double gersh = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double left = (i > 0 || periodic) ? b[(i + n - 1) % n] : 0.0;
+        gersh = std::max(gersh, a[i] + left + b[i]);
+    }
+    if (periodic) return gersh;
+    double lo = 0.0, hi = gersh;
+    for (int it = 0; it < 64; ++it) {
+        const double x = 0.5 * (lo + hi);
+        int below = 0;  // eigenvalues below x
+        double d = 1.0;
+        for (int i = 0; i < n; ++i) {
+            d = (a[i] - x) - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++below;
+        }
+        if (below == n) hi = x;
+        else lo = x;
+    }
+    return hi;
+}
+
+// Explicit-step limits of the SSP-RK3 update (Eq. 58) with the fixed dt.  The
+// scheme is stable for eigenvalues of the linearised residual down to -2.51 on
+// the negative real axis and within sqrt(3) along the imaginary axis.  On the
+// compact stencils the fluxes reduce to (Sec. 2.4), a diffusivity D along both
+// directions has eigenvalues down to -D (lx + ly), lx and ly the radii of
+// diffusion_radius, and the fourth-order Cahn-Hilliard operator M_c kappa
+// lap^2 down to -M_c kappa (lx + ly)^2.  The limits:
+//   heat       D = largest lambda / (rho C_p) of the phases (Eq. 4), odd walls
+//              where the temperature is held;
+//   momentum   D = 2 mu / rho (largest of the phases) + c_s^2 delta_t, the
+//              compressive viscous mode of the flux (its face state adds
+//              c_s^2 delta_t), odd walls except outlets;
+//   phase      M_c (kappa l^2 + 2 beta l), l = lx + ly with mirrored walls,
+//              2 beta the largest curvature of the double well (Sec. 2.3.1);
+//   acoustic   c_s dt (1/wx + 1/wy) <= sqrt(3), wx, wy the smallest widths.
+// Returns the first limit exceeded as text ("" if none).
+std::string step_limits(const eulbfs_params* p)
+{
+    const bool px = p->bc[0].periodic != 0, py = p->bc[2].periodic != 0;
+    auto radius = [&](bool xdir, auto odd) {
+        const int s0 = xdir ? 0 : 2;
+        return xdir ? diffusion_radius(p->x_width, p->dx, p->nx, px, odd(p->bc[s0]), odd(p->bc[s0 + 1]))
+                    : diffusion_radius(p->y_width, p->dx, p->ny, py, odd(p->bc[s0]), odd(p->bc[s0 + 1]));
+    };
+    auto held_T = [](const eulbfs_bc& b) { return b.heat == EULBFS_HEAT_DIRICHLET; };
+    auto held_M = [](const eulbfs_bc& b) { return b.flow != EULBFS_FLOW_OUTLET; };
+    auto mirror = [](const eulbfs_bc&) { return false; };
+    const double l_heat = radius(true, held_T) + radius(false, held_T);
+    const double l_mom = radius(true, held_M) + radius(false, held_M);
+    const double l_ch = radius(true, mirror) + radius(false, mirror);
+    double d_heat = 0.0, nu = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        d_heat = std::max(d_heat, p->lambda[k] / (p->rho[k] * p->cp[k]));
+        nu = std::max(nu, p->mu[k] / p->rho[k]);
+    }
+    const double d_mom = 2.0 * nu + p->delta_t / 3.0;
+    const double beta = 12.0 * p->sigma / p->xi, kappa = 1.5 * p->xi * p->sigma;
+    const double wx = min_width(p->x_width, p->dx, p->nx), wy = min_width(p->y_width, p->dx, p->ny);
+    const double re_bound = 2.51, im_bound = std::sqrt(3.0);
+    const double v_heat = p->dt * d_heat * l_heat, v_mom = p->dt * d_mom * l_mom;
+    const double v_ch = p->dt * p->mobility * (kappa * l_ch * l_ch + 2.0 * beta * l_ch);
+    const double v_ac = p->dt * std::sqrt(1.0 / 3.0) * (1.0 / wx + 1.0 / wy);
+    char buf[160];
+    auto over = [&](const char* what, double v, double bound) {
+        std::snprintf(buf, sizeof buf, "dt = %g is beyond the %s limit of the explicit RK3 step (%.4g > %.4g)",
+                      p->dt, what, v, bound);
+        return std::string(buf);
+    };
+    if (v_heat > re_bound) return over("thermal diffusion", v_heat, re_bound);
+    if (v_mom > re_bound) return over("viscous", v_mom, re_bound);
+    if (v_ch > re_bound) return over("Cahn-Hilliard", v_ch, re_bound);
+    if (v_ac > im_bound) return over("acoustic", v_ac, im_bound);
+    return "";
+}
+
 std::string check(const eulbfs_params* p)
 {
     if (!p) return "params is NULL";
@@ -111,6 +216,7 @@ std::string check(const eulbfs_params* p)
     if (!(p->sigma >= 0)) return "sigma must be >= 0";
     if (!(p->xi > 0)) return "xi must be > 0";
     if (!(p->mobility >= 0) || !(p->Qg > 0)) return "mobility must be >= 0 and Qg > 0";
+    if (!(p->xi >= 2.0 * wmin)) return "xi must span at least two cells (2 dx; the smallest width on a stretched mesh)";
     for (int a = 0; a < 2; ++a) {
         const eulbfs_bc& lo = p->bc[2 * a];
         const eulbfs_bc& hi = p->bc[2 * a + 1];
@@ -131,7 +237,7 @@ std::string check(const eulbfs_params* p)
     bool ok = false;
     for (auto& t : tiles) ok |= (p->tile_x == t[0] && p->tile_y == t[1]);
     if (!ok) return "tile must be 0x0, 32x8, 64x4, 16x16, 64x8, 32x16 or 32x32";
-    return "";
+    return step_limits(p);
 }
 
 int tile_of(const eulbfs_params* p)
@@ -516,16 +622,37 @@ void diag_from_sums(const eulbfs_solver* h, const double r[NRED], double* out)
     // a stretched mesh weights each cell inside the sums
     const bool nu = h->dp.mside != nullptr;
     const double dV = nu ? 1.0 : h->prm.dx * h->prm.dx;
-    out[0] = r[0] * dV;
-    out[1] = r[1] * dV;
-    out[2] = r[2] * dV;
-    out[3] = r[3] * dV;
-    out[4] = r[4];
-    out[5] = r[5];
-    out[6] = nu ? r[6] : r[6] * h->prm.dx;
+    const double dl = nu ? 1.0 : h->prm.dx;
+    out[0] = r[RED_RHO] * dV;
+    out[1] = r[RED_C] * dV;
+    out[2] = r[RED_H] * dV;
+    out[3] = r[RED_FS] * dV;
+    out[4] = r[RED_UMAX];
+    out[5] = r[RED_NONFINITE];
+    out[6] = r[RED_TIP] * dl;
     out[7] = (double)h->steps * h->prm.dt;
     out[8] = (double)h->steps;
     out[9] = h->prm.dt;
+    out[10] = -r[RED_NEG_CMIN];
+    out[11] = r[RED_CMAX];
+    out[12] = r[RED_WALL] * dl;
+    out[13] = r[RED_AXIS] * dl;
+}
+
+// Watchdog on a diagnostics record: "" when the state is usable, else why not.
+// F_s = clamp(C) (1 - F_l) lies in [0, 1] by construction, so the range check
+// is on the order parameter it is built from.
+std::string unstable_reason(const double d[EULBFS_NDIAG])
+{
+    if (d[5] != 0.0 || !std::isfinite(d[0]) || !std::isfinite(d[2]))
+        return "non-finite values in the state";
+    if (!(d[4] <= 1.0 / std::sqrt(3.0)))
+        return "speed " + std::to_string(d[4]) + " above the lattice sound speed";
+    if (!(d[10] >= -EULBFS_C_MARGIN && d[11] <= 1.0 + EULBFS_C_MARGIN))
+        return "order parameter outside [" + std::to_string(-EULBFS_C_MARGIN) + ", " +
+               std::to_string(1.0 + EULBFS_C_MARGIN) + "] (min " + std::to_string(d[10]) + ", max " +
+               std::to_string(d[11]) + ")";
+    return "";
 }
 
 template <typename R>
@@ -869,22 +996,27 @@ int eulbfs_step(eulbfs_t h, int64_t nsteps)
     return h->prm.precision == EULBFS_FP32 ? enqueue_steps<float>(h, nsteps) : enqueue_steps<double>(h, nsteps);
 }
 
-int eulbfs_run(eulbfs_t h, int64_t nsteps)
+int eulbfs_run(eulbfs_t h, int64_t nsteps, double t_end)
 {
+    if (!h) return set_err(nullptr, EULBFS_EINVAL, "handle is NULL");
+    if (nsteps < 0) return set_err(&h->err, EULBFS_EINVAL, "nsteps must be >= 0");
+    if (std::isnan(t_end)) return set_err(&h->err, EULBFS_EINVAL, "t_end is NaN");
+    // the fixed step reaches t_end after ceil((t_end - t) / dt) more steps
+    // (to a relative 1e-12, so that t_end = t + k dt takes exactly k steps)
+    const double t = (double)h->steps * h->prm.dt;
+    if (t_end < INFINITY) {
+        const double k = std::ceil((t_end - t) / h->prm.dt * (1.0 - 1e-12));
+        nsteps = std::min(nsteps, (int64_t)std::max(0.0, std::min(k, 9.0e18)));
+    }
     int rc = eulbfs_step(h, nsteps);
     if (rc != EULBFS_OK) return rc;
     double d[EULBFS_NDIAG];
     rc = h->prm.precision == EULBFS_FP32 ? do_diag<float>(h, d) : do_diag<double>(h, d);
     if (rc != EULBFS_OK) return rc;
-    if (d[5] != 0.0 || !std::isfinite(d[0]) || !std::isfinite(d[2])) {
+    const std::string why = unstable_reason(d);
+    if (!why.empty()) {
         h->poisoned = true;
-        return set_err(&h->err, EULBFS_EUNSTABLE, "non-finite values in the state after step " + std::to_string(h->steps));
-    }
-    if (!(d[4] <= 1.0 / std::sqrt(3.0))) {
-        h->poisoned = true;
-        return set_err(&h->err, EULBFS_EUNSTABLE,
-                       "speed " + std::to_string(d[4]) + " above the lattice sound speed after step " +
-                           std::to_string(h->steps));
+        return set_err(&h->err, EULBFS_EUNSTABLE, why + " after step " + std::to_string(h->steps));
     }
     return EULBFS_OK;
 }
@@ -904,11 +1036,20 @@ int eulbfs_query(eulbfs_t h, int32_t what, void* out, size_t bytes, int32_t out_
         } else {
             std::memcpy(out, d, sizeof d);
         }
+        const std::string why = unstable_reason(d);
+        if (!why.empty()) {
+            h->poisoned = true;
+            return set_err(&h->err, EULBFS_EUNSTABLE, why + " at step " + std::to_string(h->steps));
+        }
+        if (h->poisoned) return set_err(&h->err, EULBFS_EUNSTABLE, "state is unstable; restore a checkpoint");
         return EULBFS_OK;
     }
     if (what < 0 || what > EULBFS_FIELD_W_GHOSTED) return set_err(&h->err, EULBFS_EINVAL, "unknown selector");
-    return h->prm.precision == EULBFS_FP32 ? do_query_field<float>(h, what, out, bytes, out_on_device)
-                                           : do_query_field<double>(h, what, out, bytes, out_on_device);
+    const int rc = h->prm.precision == EULBFS_FP32 ? do_query_field<float>(h, what, out, bytes, out_on_device)
+                                                   : do_query_field<double>(h, what, out, bytes, out_on_device);
+    if (rc == EULBFS_OK && h->poisoned)
+        return set_err(&h->err, EULBFS_EUNSTABLE, "state is unstable; restore a checkpoint");
+    return rc;
 }
 
 int eulbfs_set_field(eulbfs_t h, int32_t what, const void* in, size_t bytes, int32_t in_on_device)
@@ -1389,6 +1530,11 @@ int eulbfs_batch_query(eulbfs_batch_t b, int32_t slot, int32_t what, void* out, 
     if (what == EULBFS_SCALAR_DIAG && !out_on_device && out && bytes >= EULBFS_NDIAG * sizeof(double) &&
         slot_settled(b, *sl)) {  // summed by the finishing tick: no wait
         diag_from_sums(sl->s, b->h_sums + (size_t)slot * NRED, (double*)out);
+        const std::string why = unstable_reason((const double*)out);
+        if (!why.empty()) {
+            sl->s->poisoned = true;
+            return set_err(&b->err, EULBFS_EUNSTABLE, why + " at the end of the request");
+        }
         return EULBFS_OK;
     }
     const int rc = eulbfs_query(sl->s, what, out, bytes, out_on_device);

@@ -56,7 +56,14 @@ struct BatchDesc {
     int tile0;
 };
 
-constexpr int NRED = 7;  // sum rho, sum C, sum H, sum F_s, max |u|, non-finite, tip column
+// Slots of the FP64 reduction: sums of rho, C, H and F_s over the cells,
+// max |u|, the count of non-finite cells, F_s and clamped C summed up the
+// middle column (tip and axis heights), max of -C and of C, clamped C summed
+// along the first row (wetted length on the y- wall).
+enum {
+    RED_RHO = 0, RED_C, RED_H, RED_FS, RED_UMAX, RED_NONFINITE, RED_TIP,
+    RED_NEG_CMIN, RED_CMAX, RED_WALL, RED_AXIS, NRED
+};
 
 template <typename R>
 hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, const State<R>& in,

@@ -774,12 +774,26 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// partial layout: [block][NRED]: sum rho, sum C, sum H, sum Fs, max|u|, nonfinite, tip
+// partial layout: [block][NRED] (RED_* slots); RED_UMAX, RED_NEG_CMIN and
+// RED_CMAX are maxima, the others sums.  The order parameter's extremes start
+// at -1e300 so that a block without cells leaves them out of the maxima.
+__device__ __forceinline__ constexpr bool red_is_max(int k)
+{
+    return k == RED_UMAX || k == RED_NEG_CMIN || k == RED_CMAX;
+}
+
+__device__ __forceinline__ void red_init(double acc[NRED])
+{
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) acc[k] = k == RED_NEG_CMIN || k == RED_CMAX ? -1e300 : 0.0;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(DevParams P, State<R> S, double* partial)
 {
     __shared__ double sred[RED_THREADS / 64][NRED];
-    double acc[NRED] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[NRED];
+    red_init(acc);
     const size_t n = (size_t)P.nx * P.ny;
     const int ic = P.nx / 2;
     for (size_t s = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; s < n; s += (size_t)gridDim.x * RED_THREADS) {
@@ -793,28 +807,35 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(DevParams P, Sta
         const double u = 3.0 * (double)w.mx / rho, v = 3.0 * (double)w.my / rho;
         // stretched mesh: cell volume and height inside the sums (uniform: dx^2 and dx after them)
         const double hy = P.mside ? 2.0 * P.myc[MESH_HW * P.msy + j + NG] : 1.0;
-        const double dV = P.mside ? 2.0 * P.mxc[MESH_HW * P.msx + i + NG] * hy : 1.0;
-        acc[0] += rho * dV;
-        acc[1] += w.C * dV;
-        acc[2] += w.H * dV;
-        acc[3] += Fs * dV;
-        acc[4] = fmax(acc[4], sqrt(u * u + v * v));
+        const double wx = P.mside ? 2.0 * P.mxc[MESH_HW * P.msx + i + NG] : 1.0;
+        const double dV = wx * hy;
+        acc[RED_RHO] += rho * dV;
+        acc[RED_C] += w.C * dV;
+        acc[RED_H] += w.H * dV;
+        acc[RED_FS] += Fs * dV;
+        acc[RED_UMAX] = fmax(acc[RED_UMAX], sqrt(u * u + v * v));
         const bool finite = isfinite(w.H) && isfinite((double)w.p) && isfinite((double)w.mx) &&
                             isfinite((double)w.my) && isfinite(w.C);
-        acc[5] += finite ? 0.0 : 1.0;
-        if (i == ic) acc[6] += Fs * hy;
+        acc[RED_NONFINITE] += finite ? 0.0 : 1.0;
+        acc[RED_NEG_CMIN] = fmax(acc[RED_NEG_CMIN], -w.C);
+        acc[RED_CMAX] = fmax(acc[RED_CMAX], w.C);
+        if (i == ic) {
+            acc[RED_TIP] += Fs * hy;
+            acc[RED_AXIS] += Cc * hy;
+        }
+        if (j == 0) acc[RED_WALL] += Cc * wx;
     }
     const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
 #pragma unroll
     for (int k = 0; k < NRED; ++k) {
-        const double r = k == 4 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        const double r = red_is_max(k) ? wave_max(acc[k]) : wave_sum(acc[k]);
         if (lane == 0) sred[wv][k] = r;
     }
     __syncthreads();
     if (threadIdx.x < NRED) {
         const int k = threadIdx.x;
         double r = sred[0][k];
-        for (int w = 1; w < RED_THREADS / 64; ++w) r = k == 4 ? fmax(r, sred[w][k]) : r + sred[w][k];
+        for (int w = 1; w < RED_THREADS / 64; ++w) r = red_is_max(k) ? fmax(r, sred[w][k]) : r + sred[w][k];
         partial[(size_t)blockIdx.x * NRED + k] = r;
     }
 }
@@ -822,21 +843,22 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(DevParams P, Sta
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double* partial, int nblocks, double* out)
 {
     __shared__ double sred[RED_THREADS / 64][NRED];
-    double acc[NRED] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[NRED];
+    red_init(acc);
     for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
         for (int k = 0; k < NRED; ++k)
-            acc[k] = k == 4 ? fmax(acc[k], partial[(size_t)b * NRED + k]) : acc[k] + partial[(size_t)b * NRED + k];
+            acc[k] = red_is_max(k) ? fmax(acc[k], partial[(size_t)b * NRED + k]) : acc[k] + partial[(size_t)b * NRED + k];
     const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
 #pragma unroll
     for (int k = 0; k < NRED; ++k) {
-        const double r = k == 4 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        const double r = red_is_max(k) ? wave_max(acc[k]) : wave_sum(acc[k]);
         if (lane == 0) sred[wv][k] = r;
     }
     __syncthreads();
     if (threadIdx.x < NRED) {
         const int k = threadIdx.x;
         double r = sred[0][k];
-        for (int w = 1; w < RED_THREADS / 64; ++w) r = k == 4 ? fmax(r, sred[w][k]) : r + sred[w][k];
+        for (int w = 1; w < RED_THREADS / 64; ++w) r = red_is_max(k) ? fmax(r, sred[w][k]) : r + sred[w][k];
         out[k] = r;
     }
 }

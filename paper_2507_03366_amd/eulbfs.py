@@ -19,12 +19,13 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, 
 FP64, FP32 = 0, 1
 KERNEL_FUSED, KERNEL_SPLIT, KERNEL_AUTO = 0, 1, 2
 INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
-ABI_VERSION = 4
+ABI_VERSION = 5
 FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
              W_GHOSTED=14)
 SCALAR_DIAG = 100
-NDIAG = 10
-DIAG_NAMES = ("mass", "volume_C", "enthalpy", "solid", "umax", "nonfinite", "tip", "time", "steps", "dt")
+NDIAG = 14
+DIAG_NAMES = ("mass", "volume_C", "enthalpy", "solid", "umax", "nonfinite", "tip", "time", "steps", "dt",
+              "c_min", "c_max", "wetted_length", "axis_height")
 
 
 class EulbfsError(RuntimeError):
@@ -77,7 +78,7 @@ def lib():
         L.eulbfs_workspace_bytes.restype = sz
         L.eulbfs_create.argtypes = [pp, ct.POINTER(eulbfs_init), vp, sz, vp, ct.POINTER(vp)]
         L.eulbfs_step.argtypes = [vp, ct.c_int64]
-        L.eulbfs_run.argtypes = [vp, ct.c_int64]
+        L.eulbfs_run.argtypes = [vp, ct.c_int64, ct.c_double]
         L.eulbfs_query.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
         L.eulbfs_set_field.argtypes = [vp, ct.c_int32, vp, sz, ct.c_int32]
         L.eulbfs_residual.argtypes = [vp, dp, dp, dp, ct.c_int32]
@@ -182,8 +183,8 @@ def eulbfs_step(h, nsteps: int) -> None:
     _raise(lib().eulbfs_step(h, int(nsteps)), h)
 
 
-def eulbfs_run(h, nsteps: int) -> None:
-    _raise(lib().eulbfs_run(h, int(nsteps)), h)
+def eulbfs_run(h, nsteps: int, t_end: float = float("inf")) -> None:
+    _raise(lib().eulbfs_run(h, int(nsteps), float(t_end)), h)
 
 
 def eulbfs_query(h, what: int, nx: int, ny: int) -> np.ndarray:
@@ -272,8 +273,8 @@ class Solver:
     def step(self, n: int):
         eulbfs_step(self.h, n)
 
-    def run(self, n: int):
-        eulbfs_run(self.h, n)
+    def run(self, n: int, t_end: float = float("inf")):
+        eulbfs_run(self.h, n, t_end)
 
     def field(self, name: str) -> np.ndarray:
         return eulbfs_query(self.h, FIELD[name], self.nx, self.ny)

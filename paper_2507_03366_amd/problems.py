@@ -315,6 +315,44 @@ TABLE3 = {
 }
 
 
+# Table 1 (Sec. 3.3): water, (liquid, solid), SI units
+TABLE1 = {"rho": (1000.0, 917.0), "cp": (4210.0, 2030.0), "lam": (0.56, 2.20), "latent": 334000.0,
+          "T_m": 0.0, "T_w": -20.0, "T_0": 20.0}
+
+
+def film_table1(ratio: float = 0.917, nx: int = 200, ny: int = 400, H0: float = 100.0, alpha_l: float = 0.05,
+                **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.3: a water film (Table 1) in a 2-D container on the paper's 200 x 400
+    grid, cooled from the left and bottom walls (T_w = -20 C), liquid and gas at
+    T_0 = 20 C, a symmetry plane on the right (free slip, adiabatic) and an outlet
+    at the top (adiabatic); no-flux phase field on every wall.  Lattice map as for
+    the Table 3 fluids: rho_l = C_p,l = 1, the solid keeps the printed C_p and
+    lambda ratios and rho_s/rho_l = `ratio` (Table 2 runs 1 and 0.917), T_m - T_w
+    -> 1, L -> L / (C_p,l (T_m - T_w)), alpha_l = 0.05, mu_l = 0.05.  The paper
+    prints no film height (H0 cells here), no surface tension in lattice units
+    (0.01, as the 256 x 256 film) and no gas data (the gas of the other
+    configurations)."""
+    m = TABLE1
+    cpl, cps = m["cp"]
+    laml, lams = m["lam"]
+    dT = m["T_m"] - m["T_w"]
+    lam_l = alpha_l
+    lam_s = lam_l * lams / laml
+    mu_l = 0.05
+    rho_g = RHO_G
+    pr = Problem(
+        nx=nx, ny=ny, rho=(ratio, 1.0, rho_g), mu=(mu_l, mu_l, _gas_mu(mu_l, rho_g)),
+        lam=(lam_s, lam_l, _gas_lambda(lam_l, rho_g)), cp=(cps / cpl, 1.0, 1.0), latent=m["latent"] / (cpl * dT),
+        sigma=0.01,
+        walls={"x-": Wall(NOSLIP, DIRICHLET, -1.0), "y-": Wall(NOSLIP, DIRICHLET, -1.0),
+               "x+": Wall(FREESLIP, ADIABATIC), "y+": Wall(OUTLET, ADIABATIC)},
+    ).replace(**kw)
+    _, Y = cell_centres(pr)
+    st = uniform_state(pr, T0=(m["T_0"] - m["T_m"]) / dT)
+    st.C = layer_profile(Y, H0, pr.xi)
+    return pr, st
+
+
 def table3_droplet(fluid: str, theta_deg: float, ratio: float = None, nx: int = 400, ny: int = 200,
                    R: float = 50.0, alpha_l: float = 0.05, **kw) -> Tuple[Problem, InitialState]:
     """Sec. 3.4 volume-change runs (Figs. 11-12): a sessile droplet of one of the

@@ -128,9 +128,13 @@ def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int =
                     time.sleep(0.0005)  # everything resident is enqueued; wait for results
                 for slot in batch.poll():
                     r = resident.pop(slot)
-                    d = batch.diagnostics(slot)
+                    try:
+                        d = batch.diagnostics(slot)
+                        ok = d["nonfinite"] == 0 and d["steps"] == r.nsteps
+                    except E.EulbfsError:  # the watchdog found the request unstable
+                        ok = False
                     finish[r.rid] = time.perf_counter() - t0
-                    if d["nonfinite"] != 0 or d["steps"] != r.nsteps:
+                    if not ok:
                         failed.append(r.rid)
                     batch.release(slot)
                     enqueued.pop(slot, None)
@@ -156,11 +160,12 @@ def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None)
 
     if stream is None:
         stream = torch.cuda.Stream()
+    order = sorted(requests, key=lambda q: q.arrival)
+    built = [build(r, precision) for r in order]  # host-side inputs, outside the timed window as in serve()
     t0 = time.perf_counter()
     lat, failed = [], []
     cells = 0
-    for r in sorted(requests, key=lambda q: q.arrival):
-        pr, st = build(r, precision)
+    for r, (pr, st) in zip(order, built):
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
@@ -168,9 +173,12 @@ def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None)
         try:
             s.step(r.nsteps)
             d = s.diagnostics()
+            ok = d["nonfinite"] == 0
+        except E.EulbfsError:  # the watchdog found the request unstable
+            ok = False
         finally:
             s.close()
-        if d["nonfinite"] != 0:
+        if not ok:
             failed.append(r.rid)
         lat.append(time.perf_counter() - t0 - r.arrival)
         cells += pr.cells * r.nsteps
@@ -181,8 +189,65 @@ def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None)
             "precision": "fp32" if precision == E.FP32 else "fp64"}
 
 
+def accuracy(requests: List[Request], *, max_slots: int = 64, hbm_budget: int = 2 << 30, tick_steps: int = 100,
+             stream=None) -> dict:
+    """The served FP32 results against FP64: every request of the list runs
+    through one FP32 batch (as served) and alone in FP64 (as the sequential
+    baseline runs it); per request the relative L2 difference of each conserved
+    field (H, p, the momentum vector, C) and the difference of the tip height
+    and of the axis height (diagnostics 6 and 13), in cells."""
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.Stream()
+    rows = []
+    batch = E.Batch(hbm_budget, max_slots, precision=E.FP32, stream=stream)
+    try:
+        slots = {}
+        for r in requests:
+            pr, st = build(r, E.FP32)
+            slot = batch.admit(pr, st, r.nsteps)
+            if slot is None:
+                raise RuntimeError("the accuracy subset must fit one batch")
+            slots[r.rid] = slot
+        nsteps = max(r.nsteps for r in requests)
+        for _ in range((nsteps + tick_steps - 1) // tick_steps):
+            batch.tick(tick_steps)
+        stream.synchronize()
+        assert len(batch.poll()) == len(requests)
+        served = {rid: (batch.conserved(sl), batch.diagnostics(sl)) for rid, sl in slots.items()}
+    finally:
+        batch.close()
+    for r in requests:
+        pr, st = build(r, E.FP64)
+        s = E.Solver(pr, st, precision=E.FP64, kernel=E.KERNEL_AUTO, stream=stream)
+        try:
+            s.step(r.nsteps)
+            w64, d64 = s.conserved(), s.diagnostics()
+        finally:
+            s.close()
+        w32, d32 = served[r.rid]
+        err = {}
+        for name, ks in (("H", [0]), ("p", [1]), ("M", [2, 3]), ("C", [4])):
+            den = np.linalg.norm(w64[ks].ravel())
+            err[name] = float(np.linalg.norm((w32[ks] - w64[ks]).ravel()) / den) if den > 0 else 0.0
+        rows.append({"rid": r.rid, "n": r.n, "kind": r.kind, "rel_l2": err,
+                     "tip_cells": abs(d32["tip"] - d64["tip"]) / pr.dx,
+                     "axis_cells": abs(d32["axis_height"] - d64["axis_height"]) / pr.dx})
+    worst = [max(row["rel_l2"].values()) for row in rows]
+    fronts = [max(row["tip_cells"], row["axis_cells"]) for row in rows]
+    return {"requests": len(rows), "steps_per_request": requests[0].nsteps if requests else 0,
+            "rids": [row["rid"] for row in rows],
+            "max_rel_l2": {k: max(row["rel_l2"][k] for row in rows) for k in ("H", "p", "M", "C")},
+            "median_rel_l2": float(np.median(worst)), "max_front_cells": max(fronts),
+            "median_front_cells": float(np.median(fronts)),
+            "within_bar": bool(max(worst) <= 1e-4 and max(fronts) <= 0.5),
+            "bar": "relative L2 <= 1e-4 per field, tip and axis heights within 0.5 cell"}
+
+
 def run_mix(count: int = 256, nsteps: int = 2000, seed: int = 0, load: float = 0.8, hbm_budget: int = 2 << 30,
-            max_slots: int = 64, tick_steps: int = 100, sizes=SIZES, with_sequential: bool = True) -> dict:
+            max_slots: int = 64, tick_steps: int = 100, sizes=SIZES, with_sequential: bool = True,
+            accuracy_requests: int = 24) -> dict:
     """The serving benchmark: (1) all requests at t = 0 through the batched
     FP32 server (capacity), (2) Poisson arrivals at `load` times that capacity
     (latency under load), (3) the sequential FP64 baseline on the burst."""
@@ -200,6 +265,12 @@ def run_mix(count: int = 256, nsteps: int = 2000, seed: int = 0, load: float = 0
         reqs3 = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
         out["sequential_fp64_burst"] = sequential(reqs3)
         out["speedup_solves_per_s"] = burst["solves_per_s"] / out["sequential_fp64_burst"]["solves_per_s"]
+    if accuracy_requests:
+        # every (count // accuracy_requests)-th request of the mix
+        reqs4 = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
+        step = max(1, count // accuracy_requests)
+        out["accuracy_fp32_vs_fp64"] = accuracy(reqs4[::step][:accuracy_requests], max_slots=max_slots,
+                                                hbm_budget=hbm_budget, tick_steps=tick_steps)
     return out
 
 

@@ -37,8 +37,15 @@ def test_bench_json_line():
     if rl["frac"] is not None:
         assert 0 < rl["frac"] < 1 and 0 < rl["valu_issue_frac"] < 1
     assert d["serving"]["batched_fp32_burst"]["failed"] == []
+    acc = d["serving"]["accuracy_fp32_vs_fp64"]
+    assert acc["requests"] == 6 and acc["within_bar"], acc
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
+    assert cb["one_thread"]["value"] > 0 and cb["cpu_model"]
+    sweep = d["hbm_sweep"]
+    assert [p["workload"] for p in sweep] == ["4096x4096", "4096x4096", "64 x 512x512 batch"]
+    for p in sweep:
+        assert p["working_set_mb"] > 256 and 0 < p["frac"] < 1 and p["mlups"] > 0
 
 
 @pytest.mark.gpu
@@ -46,7 +53,7 @@ def test_bench_stretched_workload():
     """The graded-mesh droplet runs through the same contract (fused 32x16
     tiles, a CPU baseline from the oracle on the same stretched mesh)."""
     r = subprocess.run([sys.executable, "-u", str(ROOT / "bench.py"), "--workload", "G512", "--steps", "3",
-                        "--warmup", "1", "--serving", "0", "--cpu-budget", "1"],
+                        "--warmup", "1", "--serving", "0", "--cpu-budget", "1", "--no-hbm-sweep"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.startswith("{")]

@@ -42,7 +42,9 @@ def test_struct_layout_matches_header():
 
 
 def _params(**kw):
-    pr, _ = PB.static_droplet(n=64, R=16)
+    # the surface tension of the 512 x 512 droplet (Ca on R = 16 would put the
+    # Cahn-Hilliard step beyond the explicit limit at dt = 0.5)
+    pr, _ = PB.static_droplet(n=64, R=16, sigma=0.015625)
     return E.params_from_problem(pr.replace(**kw))
 
 
@@ -52,7 +54,8 @@ def test_valid_parameters_pass_and_size_the_workspace():
     fp64 = E.eulbfs_workspace_bytes(P)
     # W^n, two RK registers, dF_s/dt: 16 planes of 64 x 64 doubles at least
     assert fp64 >= 16 * 64 * 64 * 8
-    P32 = E.params_from_problem(PB.static_droplet(n=64, R=16)[0], precision=E.FP32)
+    P32 = E.params_from_problem(PB.static_droplet(n=64, R=16, sigma=0.015625)[0], precision=E.FP32)
+    assert E.eulbfs_check_params(P32) == ""
     assert E.eulbfs_workspace_bytes(P32) < fp64
 
 
@@ -133,7 +136,7 @@ def test_stretched_mesh_parameters():
     beside what the uniform mesh needs."""
     import numpy as np
 
-    pr, _ = PB.static_droplet(n=64, R=16)
+    pr, _ = PB.static_droplet(n=64, R=16, sigma=0.015625, dt=0.3)
     w = np.linspace(0.6, 1.4, 64)
     P = E.params_from_problem(pr.replace(x_width=w, delta_t=0.3), kernel=E.KERNEL_AUTO)
     assert E.eulbfs_check_params(P) == ""
@@ -150,3 +153,65 @@ def test_stretched_mesh_parameters():
     bad[5] = np.nan
     P = E.params_from_problem(pr.replace(y_width=bad, delta_t=0.1), kernel=E.KERNEL_SPLIT)
     assert "widths" in E.eulbfs_check_params(P)
+
+
+def test_interface_width_of_two_cells():
+    """xi below two cells cannot hold the Eq. (61) profile."""
+    assert "xi" in E.eulbfs_check_params(_params(xi=1.9))
+    assert E.eulbfs_check_params(_params(xi=2.0)) == ""
+
+
+def test_update_step_beyond_the_explicit_limits_is_rejected():
+    """dt is checked at create against the SSP-RK3 stability bounds of each
+    diffusive process on the actual mesh: a gas 1000 times lighter than the
+    liquid with 1/100 of its viscosity (kinematic viscosity 0.5) at dt = 0.5,
+    the Cahn-Hilliard step of a Table 3 droplet whose surface tension is taken
+    from Ca on a four times smaller radius, a thermal diffusivity of 1 on the
+    0.6-wide cells of a graded mesh, and an acoustic step beyond sqrt(3)."""
+    import numpy as np
+
+    pr, _ = PB.three_phase_stefan()
+    assert E.eulbfs_check_params(E.params_from_problem(pr)) == ""
+    bad = pr.replace(mu=(0.05, 0.05, 0.0005), rho=(0.917, 1.0, 0.001))
+    assert "viscous" in E.eulbfs_check_params(E.params_from_problem(bad))
+    assert E.eulbfs_check_params(E.params_from_problem(bad.replace(dt=0.2))) == ""
+    pr, _ = PB.table3_droplet("hexadecane", 150.0, ratio=1.07, alpha_l=0.3, nx=100, ny=50, R=12.5)
+    assert "Cahn-Hilliard" in E.eulbfs_check_params(E.params_from_problem(pr))
+    wy = PB.graded_widths(97, 0.6, 1.03, 1.5)
+    g = PB.Problem(nx=40, ny=97, y_width=wy, delta_t=0.3, dt=0.3, rho=(1.0, 1.0, 0.01), lam=(1.0, 1.0, 0.01),
+                   mu=(0.01, 0.01, 0.0001),
+                   walls={"y-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -1.0)})
+    assert "thermal" in E.eulbfs_check_params(E.params_from_problem(g))
+    assert E.eulbfs_check_params(E.params_from_problem(g.replace(lam=(0.4, 0.4, 0.004)))) == ""
+    # acoustic: c_s dt (1/dx + 1/dy) <= sqrt(3) with everything else inviscid and insulating
+    quiet = dict(mu=(0.0, 0.0, 0.0), lam=(0.0, 0.0, 0.0), sigma=0.0, delta_t=0.01)
+    a = PB.Problem(nx=8, ny=8, periodic_x=True, periodic_y=True, dt=1.45, **quiet)
+    assert E.eulbfs_check_params(E.params_from_problem(a)) == ""
+    assert "acoustic" in E.eulbfs_check_params(E.params_from_problem(a.replace(dt=1.55)))
+
+
+def test_diffusion_radius_matches_the_matrix_eigenvalues():
+    """The stability check's eigenvalue bound against numpy on the same 1-D
+    operators: the bound admits a step at 0.999 of the limit and rejects one at
+    1.001 of it, for a graded mesh with a Dirichlet wall."""
+    import numpy as np
+
+    wy = PB.graded_widths(60, 0.5, 1.05, 1.5)
+    n = len(wy)
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j in (i - 1, i + 1):
+            if 0 <= j < n:
+                h = 0.5 * (wy[i] + wy[j])
+                A[i, i] += 1 / (wy[i] * h)
+                A[i, j] -= 1 / (wy[i] * h)
+        if i == 0:
+            A[i, i] += 2 / (wy[i] ** 2)  # held temperature at the wall
+    lam_y = np.max(np.linalg.eigvals(A).real)
+    lam_x = 4.0  # 8 uniform periodic cells: the largest of 4 sin^2(pi k / 8)
+    alpha = 0.4
+    dt_lim = 2.51 / (alpha * (lam_x + lam_y))
+    base = PB.Problem(nx=8, ny=n, y_width=wy, delta_t=0.2, lam=(0.4, 0.4, 0.4), mu=(0.0, 0.0, 0.0), sigma=0.0,
+                      periodic_x=True, walls={"y-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -1.0), "y+": PB.Wall()})
+    assert E.eulbfs_check_params(E.params_from_problem(base.replace(dt=0.999 * dt_lim))) == ""
+    assert "thermal" in E.eulbfs_check_params(E.params_from_problem(base.replace(dt=1.001 * dt_lim)))

@@ -136,7 +136,7 @@ def test_batch_admission_by_footprint():
         s0 = b.admit(pr, st, 10)
         assert s0 is not None
         assert b.admit(pr, st, 10) is None  # second copy does not fit
-        small, sst = PB.static_droplet(n=64, R=16)
+        small, sst = PB.static_droplet(n=64, R=16, sigma=0.015625)
         s1 = b.admit(small, sst, 10)        # a small one still fits beside it
         assert s1 is not None
         b.release(s0)

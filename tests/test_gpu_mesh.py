@@ -254,7 +254,7 @@ def test_batch_with_stretched_and_uniform_requests(oracle, precision):
     drop, drop_st = _graded_drop(precision=precision)
     box = CASES[1][1].replace(lattice_hg=5, precision=precision)
     box_st = PB.seeded_fields(box, seed=4, amp=0.5)
-    uni, uni_st = PB.static_droplet(n=64, R=16)
+    uni, uni_st = PB.static_droplet(n=64, R=16, sigma=0.015625)
     uni = uni.replace(precision=precision)
     reqs = [(drop, drop_st, 60), (box, box_st, 40), (uni, uni_st, 50)]
     b = E.Batch(1 << 28, 8, precision=precision, stream=torch.cuda.Stream())
