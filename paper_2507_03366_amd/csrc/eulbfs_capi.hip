@@ -278,6 +278,8 @@ DevParams make_dev(const eulbfs_params* p)
     d.delta_t = p->delta_t;
     d.dt = p->dt;
     d.inv_dt = 1.0 / p->dt;
+    d.half_off[0] = 0.25;
+    d.half_off[1] = 0.125;
     for (int k = 0; k < 3; ++k) {
         d.rho[k] = p->rho[k];
         d.mu[k] = p->mu[k];
@@ -1129,6 +1131,7 @@ struct Slot {
     size_t off = 0, bytes = 0;
     int64_t nsteps = 0, done = 0;
     int64_t finish_tick = -1;  // tick whose launches complete the request
+    int64_t serial = -1;       // admission number: names the request (and so its tiles) in a graph key
 };
 
 struct TickEvent {
@@ -1158,6 +1161,14 @@ struct eulbfs_batch {
     char* h_desc[2] = {nullptr, nullptr};
     int* h_tiles[2] = {nullptr, nullptr};
     hipEvent_t upload_done[2] = {nullptr, nullptr};
+    // per table set: a tick's launches (its steps x three stages x every group
+    // present) captured for the step count and requests it was captured with
+    // (their serials, in launch order), replayed while both are unchanged
+    hipGraphExec_t step_graph[2] = {nullptr, nullptr};
+    std::vector<int64_t> graph_key[2];
+    std::vector<int64_t> last_key;  // requests of the previous tick
+    bool graph_off = false;  // capture is impossible (legacy stream) or failed once
+    int64_t admitted = 0;    // admissions so far
     int parity = 0;
     int64_t tick = 0;
     std::vector<TickEvent> events;  // recent ticks
@@ -1299,12 +1310,57 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     HIP_TRY(hipEventRecord(b->upload_done[par], b->stream));
     const BatchDesc<R>* dd = reinterpret_cast<const BatchDesc<R>*>(b->d_desc[par]);
     const StageCoef K[3] = {{0.0, 1.0, 1.0, 0}, {0.75, 0.25, 0.25, 0}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 1}};
-    for (int64_t st = 0; st < s_eff; ++st)
+    auto one_step = [&]() -> hipError_t {
         for (int stage = 0; stage < 3; ++stage)
             for (int g = 0; g < NGROUP; ++g)
-                if (ntiles[g])
-                    HIP_TRY(launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g], (g & 4) ? 5 : 9,
-                                                    g & 3, g >= 8, K[stage], stage, b->stream));
+                if (ntiles[g]) {
+                    const hipError_t e = launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g],
+                                                                 (g & 4) ? 5 : 9, g & 3, g >= 8, K[stage], stage,
+                                                                 b->stream);
+                    if (e != hipSuccess) return e;
+                }
+        return hipSuccess;
+    };
+    // The launches of a tick depend only on its step count, the requests
+    // (their tables, tiles and groups) and the table set: a graph captured for
+    // them is replayed; a new set is captured again (kernel nodes only).
+    std::vector<int64_t> key{s_eff};
+    for (int k : order) key.push_back(b->slots[k].serial);
+    // a set of requests is captured once it has lasted a tick: in a busy
+    // serving mix the set changes nearly every tick, and capturing each one
+    // would cost more host time than the launches it replaces
+    const bool steady = key == b->last_key;
+    b->last_key = key;
+    bool graph = false;
+    if (!b->graph_off && b->stream != nullptr && s_eff > 1 && steady) {
+        if (b->step_graph[par] && b->graph_key[par] == key) {
+            graph = true;
+        } else {
+            if (b->step_graph[par]) (void)hipGraphExecDestroy(b->step_graph[par]);
+            b->step_graph[par] = nullptr;
+            hipGraph_t gr = nullptr;
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                hipError_t el = hipSuccess;
+                for (int64_t st = 0; st < s_eff && el == hipSuccess; ++st) el = one_step();
+                const hipError_t ec = hipStreamEndCapture(b->stream, &gr);
+                graph = el == hipSuccess && ec == hipSuccess && gr &&
+                        hipGraphInstantiate(&b->step_graph[par], gr, nullptr, nullptr, 0) == hipSuccess;
+            }
+            if (gr) (void)hipGraphDestroy(gr);
+            if (graph) {
+                b->graph_key[par] = key;
+            } else {  // launch eagerly from now on
+                if (b->step_graph[par]) (void)hipGraphExecDestroy(b->step_graph[par]);
+                b->step_graph[par] = nullptr;
+                b->graph_off = true;
+                (void)hipGetLastError();
+            }
+        }
+    }
+    if (graph)
+        HIP_TRY(hipGraphLaunch(b->step_graph[par], b->stream));
+    else
+        for (int64_t st = 0; st < s_eff; ++st) HIP_TRY(one_step());
     // requests finished by this tick: their FP64 sums go to pinned memory
     for (int k : act) {
         Slot& sl = b->slots[k];
@@ -1492,6 +1548,7 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
     }
     Slot& sl = b->slots[k];
     sl.s = h;
+    sl.serial = b->admitted++;
     sl.off = off;
     sl.bytes = bytes;
     sl.nsteps = nsteps;
@@ -1572,6 +1629,8 @@ int eulbfs_batch_destroy(eulbfs_batch_t b)
         if (b->h_tiles[k]) (void)hipHostFree(b->h_tiles[k]);
         if (b->upload_done[k]) (void)hipEventDestroy(b->upload_done[k]);
     }
+    for (int k = 0; k < 2; ++k)
+        if (b->step_graph[k]) (void)hipGraphExecDestroy(b->step_graph[k]);
     if (b->own && b->base) (void)hipFree(b->base);
     delete b;
     return EULBFS_OK;

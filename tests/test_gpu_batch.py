@@ -168,3 +168,39 @@ def test_graph_replay_matches_eager_launches():
     finally:
         a.close()
         b.close()
+
+
+def test_batch_step_graphs_match_eager_ticks():
+    """Ticks replayed from captured step graphs (a created stream) equal eager
+    ticks (the legacy default stream, where nothing is captured) bit for bit
+    while the resident set changes: a request finishes and another is admitted
+    between ticks, so the graphs are captured again; every replay is checked
+    after the host has synchronised and queried."""
+    import torch
+
+    reqs = _requests()
+
+    def drive(stream):
+        b = E.Batch(1 << 28, 8, precision=E.FP64, stream=stream)
+        seen = []
+        try:
+            a = b.admit(*reqs[0], 80)
+            c = b.admit(*reqs[3], 30)
+            for k in range(8):
+                if k == 2:
+                    d = b.admit(*reqs[1], 40)
+                b.tick(10)
+                torch.cuda.synchronize()
+                seen.append(b.conserved(a))
+                if k >= 2:
+                    seen.append(b.conserved(d))
+            seen.append(b.conserved(c))
+        finally:
+            b.close()
+        return seen
+
+    captured = drive(torch.cuda.Stream())
+    eager = drive(None)
+    assert len(captured) == len(eager)
+    for x, y in zip(captured, eager):
+        assert np.array_equal(x, y)
