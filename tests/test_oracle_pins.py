@@ -238,6 +238,19 @@ def test_conductive_freezing_matches_textbook_enthalpy_method(oracle):
     assert A.rel_l2(W[0, 0], Href) < 1e-12
 
 
+def test_conductive_freezing_d2q5_equals_d2q9(oracle):
+    """At rest (u = 0) the D2Q5 and D2Q9 enthalpy lattices carry the same heat
+    flux (their equilibria share the zeroth and first moments and the isotropic
+    second moment C_p,ref c_s^2 T), so the conductive-freezing run is the same to
+    rounding on both (the benchmark list's lattice cross-check)."""
+    oracle.set_threads(1)
+    pr, st = PB.conductive_freezing(ny=1)
+    W9, _ = oracle.run(pr, st, 2000)
+    W5, _ = oracle.run(pr.replace(lattice_hg=5), st, 2000)
+    assert A.rel_l2(W5[0], W9[0]) < 1e-13
+    assert np.abs(W9[0]).max() > 0 and np.all(W5[1:4] == 0.0) and np.all(W9[1:4] == 0.0)
+
+
 @pytest.mark.slow
 def test_conductive_freezing_neumann_front(oracle):
     """Sec. 3.1 one-phase: X(t) = 2 k sqrt(alpha t), k(Ste = 0.1); no flow at all."""
