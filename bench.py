@@ -108,6 +108,9 @@ def workload(name: str):
         pr, st = PB.static_droplet()
         desc = ("static droplet freezing on a cold wall, 512x512 cells, R=128, theta=90deg, rho_s/rho_l=0.917, "
                 "rho_g/rho_l=1e-3, Ste=0.1, Ca=0.01")
+    elif name == "C1":
+        pr, st = PB.conductive_freezing()
+        desc = "conductive freezing (one-phase Neumann), 128x4 cells, Ste=0.1, alpha=0.4"
     elif name == "C3":
         pr, st = PB.film_freezing()
         desc = "liquid film freezing, 256x256 cells, film height 0.3, Bo=1, Ste=0.05, rho_s/rho_l=0.917"
@@ -248,6 +251,73 @@ def hbm_batch_point(count: int, n: int, steps: int):
             "working_set_mb": round(count * need / 1e6, 1)}
 
 
+# Per-config windows: (workload, oracle steps on all cores, oracle steps on
+# one thread, steps to the configuration's end point or None).  C1 and C2 run
+# their full length on all cores; C3 and C4 a 1000-step window, whose
+# time to solution is extrapolated and labelled so.
+CONFIG_WINDOWS = (("C1", 20000, 20000, 20000), ("C2", 50000, 2000, 50000), ("C3", 1000, 100, 360000),
+                  ("C4", 1000, 100, None))
+
+
+def gpu_rate(pr, st, precision: int, steps: int):
+    """MLUPS of the autotuned fused kernel over `steps` steps (HIP events on
+    the solver's stream) and the seconds they took."""
+    import torch
+    from paper_2507_03366_amd import eulbfs as E
+
+    stream = torch.cuda.Stream()
+    s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream)
+    try:
+        s.step(8)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+    finally:
+        s.close()
+    return pr.cells * steps / sec / 1e6, sec
+
+
+def config_table():
+    """The oracle (all cores and one thread) and the GPU path (FP64 and FP32
+    mode) on each configuration's window."""
+    from oracle import oracle as O
+
+    O.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows = []
+    for name, n_all, n_one, n_end in CONFIG_WINDOWS:
+        pr, st, desc = workload(name)
+        row = {"config": name, "workload": desc, "cells": pr.cells}
+        O.set_threads(threads)
+        t0 = time.perf_counter()
+        O.run(pr, st, n_all)
+        el = time.perf_counter() - t0
+        row["oracle_all_cores"] = {"steps": n_all, "seconds": round(el, 2), "threads": O.num_threads(),
+                                   "mlups": round(pr.cells * n_all / el / 1e6, 3)}
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        O.run(pr, st, n_one)
+        el1 = time.perf_counter() - t0
+        row["oracle_one_thread"] = {"steps": n_one, "seconds": round(el1, 2),
+                                    "mlups": round(pr.cells * n_one / el1 / 1e6, 3)}
+        g64, s64 = gpu_rate(pr, st, 0, n_all)
+        g32, s32 = gpu_rate(pr, st, 1, n_all)
+        row["gpu_fp64"] = {"steps": n_all, "seconds": round(s64, 4), "mlups": round(g64, 1)}
+        row["gpu_fp32"] = {"steps": n_all, "seconds": round(s32, 4), "mlups": round(g32, 1)}
+        if n_end:
+            tag = "measured" if n_end == n_all else f"extrapolated from the {n_all}-step window"
+            row["time_to_solution_s"] = {"steps": n_end, "oracle_all_cores": round(n_end * el / n_all, 1),
+                                         "gpu_fp64": round(n_end * s64 / n_all, 3),
+                                         "gpu_fp32": round(n_end * s32 / n_all, 3), "how": tag}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    O.set_threads(threads)
+    return {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "configs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +337,8 @@ def main():
                     help="skip the large-grid points whose working set exceeds the 256 MB Infinity Cache")
     ap.add_argument("--only-hbm-sweep", action="store_true",
                     help="run only the large-grid points and print them (for profiling them alone)")
+    ap.add_argument("--config-table", action="store_true",
+                    help="only time the oracle and the GPU path on each configuration's window")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -290,6 +362,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 5}), flush=True)
+        return
+    if args.config_table:
+        print(json.dumps(config_table()), flush=True)
         return
     if args.only_hbm_sweep:
         print(json.dumps({"hbm_sweep": [hbm_point("R4096", 0, 60), hbm_point("R4096", 1, 60),
