@@ -333,8 +333,8 @@ size_t eulbfs_batch_request_bytes(const eulbfs_params* prm);
  * waiting for the ticks in flight.  EULBFS_EBUSY when no slot or not
  * enough contiguous arena is free; EULBFS_EINVAL for bad parameters or a
  * precision that differs from the batch's.  *slot receives the slot index.
- * The request steps with the batched kernel (tile 32 x 8) whatever its
- * kernel and tile fields say. */
+ * The request steps with the batched kernel (the batch's tile shape, below)
+ * whatever its kernel and tile fields say. */
 int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_init* init,
                        int64_t nsteps, int32_t* slot);
 
@@ -359,6 +359,35 @@ int eulbfs_batch_query(eulbfs_batch_t b, int32_t slot, int32_t what, void* out, 
 /* Free a slot and its arena range.  Waits for the stream only when the request
  * has not finished on the device (its planes may still be in use). */
 int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot);
+
+/* Tile shape of the batched kernel for requests on uniform meshes (requests
+ * on stretched meshes always take 32 x 16).  EULBFS_BATCH_TILE_AUTO, the
+ * default, picks it on the live mix: every tick's launches are timed with
+ * events, and two back-to-back ticks that advance the same requests by the
+ * same steps with different shapes give a paired sample of their time ratio.
+ * Until the first pair the ticks alternate between the shapes; then a tick
+ * runs the shape that the running geometric mean of the paired ratios
+ * favours, and every EULBFS_BATCH_EXPLORE-th tick the other one.  The fixed
+ * values pin one shape.  Every shape gives the same bits.  EULBFS_EINVAL for
+ * another value. */
+#define EULBFS_BATCH_TILE_AUTO 0
+#define EULBFS_BATCH_TILE_32x16 1
+#define EULBFS_BATCH_TILE_64x8 2
+#define EULBFS_BATCH_EXPLORE 8
+int eulbfs_batch_set_tile(eulbfs_batch_t b, int32_t tile);
+
+/* What the tile choice has measured (completed ticks only; no blocking). */
+typedef struct eulbfs_batch_sched {
+    int32_t next_tile;            /* EULBFS_BATCH_TILE_32x16 or _64x8: the shape of the next tick */
+    int32_t reserved;
+    double ns_per_cell_step[2];   /* device time per cell-step over every timed tick of each shape
+                                     (32 x 16, 64 x 8); 0 before the first */
+    int64_t ticks_timed[2];
+    double time_ratio;            /* time of 64 x 8 over 32 x 16 on paired ticks (running geometric
+                                     mean); 0 before the first pair */
+    int64_t pairs;
+} eulbfs_batch_sched;
+int eulbfs_batch_schedule(eulbfs_batch_t b, eulbfs_batch_sched* out);
 
 int eulbfs_batch_destroy(eulbfs_batch_t b);
 

@@ -1137,6 +1137,12 @@ struct Slot {
 struct TickEvent {
     hipEvent_t ev = nullptr;
     int64_t tick = -1;
+    // the tick's step launches, timed for the tile choice; sig names the work
+    // (step count and requests), so two ticks of equal sig did the same work
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int tile = 0;
+    double cell_steps = 0.0;
+    uint64_t sig = 0;
 };
 
 }  // namespace
@@ -1168,6 +1174,19 @@ struct eulbfs_batch {
     std::vector<int64_t> graph_key[2];
     std::vector<int64_t> last_key;  // requests of the previous tick
     bool graph_off = false;  // capture is impossible (legacy stream) or failed once
+    // tile shape of uniform-mesh requests (EULBFS_BATCH_TILE_*) and what the
+    // automatic choice has measured: device time and cell-steps of the timed
+    // ticks of each shape; the running mean of log(t(64x8) / t(32x16)) over
+    // back-to-back ticks of the same work; the last completed timed tick
+    int tile_mode = EULBFS_BATCH_TILE_AUTO;
+    double tile_ms[NBATCH_TILES] = {}, tile_cells[NBATCH_TILES] = {};
+    int64_t tile_ticks[NBATCH_TILES] = {};
+    double log_ratio = 0.0;
+    int64_t pairs = 0;
+    bool have_last = false;
+    uint64_t last_sig = 0;
+    int last_tile = 0;
+    double last_ns = 0.0;
     int64_t admitted = 0;    // admissions so far
     int parity = 0;
     int64_t tick = 0;
@@ -1242,9 +1261,44 @@ void batch_progress(eulbfs_batch* b, bool wait)
             break;
         }
         b->completed_tick = te.tick + 1;
+        float ms = 0.0f;
+        if (te.t0 && te.t1 && te.cell_steps > 0.0 && hipEventElapsedTime(&ms, te.t0, te.t1) == hipSuccess) {
+            const double ns = 1e6 * (double)ms / te.cell_steps;
+            b->tile_ms[te.tile] += ms;
+            b->tile_cells[te.tile] += te.cell_steps;
+            ++b->tile_ticks[te.tile];
+            if (b->have_last && b->last_sig == te.sig && b->last_tile != te.tile && b->last_ns > 0.0 && ns > 0.0) {
+                const double r = te.tile == 1 ? std::log(ns / b->last_ns) : std::log(b->last_ns / ns);
+                b->log_ratio = b->pairs == 0 ? r : b->log_ratio + 0.125 * (r - b->log_ratio);
+                ++b->pairs;
+            }
+            b->have_last = true;
+            b->last_sig = te.sig;
+            b->last_tile = te.tile;
+            b->last_ns = ns;
+        } else {
+            (void)hipGetLastError();
+            b->have_last = false;
+        }
+        if (te.t0) (void)hipEventDestroy(te.t0);
+        if (te.t1) (void)hipEventDestroy(te.t1);
         (void)hipEventDestroy(te.ev);
         b->events.erase(b->events.begin());
     }
+}
+
+// Tile shape of the next tick's uniform-mesh requests (an index into
+// BATCH_TX/BATCH_TY): the pinned one; else, until a pair of back-to-back
+// ticks of the same work has been timed on the two shapes, alternate; then
+// the shape the paired ratios favour, with every EULBFS_BATCH_EXPLORE-th
+// tick on the other.  The time of a tick depends on its requests far more
+// than on its tile, so only ticks of the same work are compared.
+int batch_pick_tile(const eulbfs_batch* b)
+{
+    if (b->tile_mode != EULBFS_BATCH_TILE_AUTO) return b->tile_mode - 1;
+    if (b->pairs == 0) return (int)(b->tick & 1);
+    const int best = b->log_ratio < 0.0 ? 1 : 0;
+    return b->tick % EULBFS_BATCH_EXPLORE == EULBFS_BATCH_EXPLORE - 1 ? 1 - best : best;
 }
 
 template <typename R>
@@ -1285,10 +1339,15 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     for (int g = 0; g < NGROUP; ++g)
         for (int k : act)
             if (group_of(b->slots[k].s) == g) order.push_back(k);
+    const int tile = batch_pick_tile(b);
     int tile_total = 0;
+    double cells = 0.0;
     for (int k : order) {
         eulbfs_solver* h = b->slots[k].s;
-        const int tx = (h->prm.nx + BATCH_TX - 1) / BATCH_TX, ty = (h->prm.ny + BATCH_TY - 1) / BATCH_TY;
+        const int tb = h->dp.mside ? 0 : tile;  // stretched meshes: always the first shape
+        const int tx = (h->prm.nx + BATCH_TX[tb] - 1) / BATCH_TX[tb];
+        const int ty = (h->prm.ny + BATCH_TY[tb] - 1) / BATCH_TY[tb];
+        cells += (double)h->prm.nx * h->prm.ny;
         if (tile_total + tx * ty > b->tile_cap) return set_err(err, EULBFS_ENOMEM, "batch tile table full");
         const int group = group_of(h);
         if (ntiles[group] == 0) first[group] = tile_total;
@@ -1315,8 +1374,8 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
             for (int g = 0; g < NGROUP; ++g)
                 if (ntiles[g]) {
                     const hipError_t e = launch_stage_batched<R>(dd, b->d_tiles[par] + first[g], ntiles[g],
-                                                                 (g & 4) ? 5 : 9, g & 3, g >= 8, K[stage], stage,
-                                                                 b->stream);
+                                                                 (g & 4) ? 5 : 9, g & 3, g >= 8, g >= 8 ? 0 : tile,
+                                                                 K[stage], stage, b->stream);
                     if (e != hipSuccess) return e;
                 }
         return hipSuccess;
@@ -1324,8 +1383,11 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
     // The launches of a tick depend only on its step count, the requests
     // (their tables, tiles and groups) and the table set: a graph captured for
     // them is replayed; a new set is captured again (kernel nodes only).
-    std::vector<int64_t> key{s_eff};
+    std::vector<int64_t> key{s_eff, tile};
     for (int k : order) key.push_back(b->slots[k].serial);
+    uint64_t sig = 1469598103934665603ull;  // FNV-1a over the step count and the requests, not the tile
+    for (size_t q = 0; q < key.size(); ++q)
+        if (q != 1) sig = (sig ^ (uint64_t)key[q]) * 1099511628211ull;
     // a set of requests is captured once it has lasted a tick: in a busy
     // serving mix the set changes nearly every tick, and capturing each one
     // would cost more host time than the launches it replaces
@@ -1357,10 +1419,21 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
             }
         }
     }
+    TickEvent te;
+    te.tile = tile;
+    te.cell_steps = cells * (double)s_eff;
+    te.sig = sig;
+    if (hipEventCreate(&te.t0) != hipSuccess || hipEventCreate(&te.t1) != hipSuccess) {
+        (void)hipGetLastError();  // untimed tick
+        if (te.t0) (void)hipEventDestroy(te.t0);
+        te.t0 = te.t1 = nullptr;
+    }
+    if (te.t0) HIP_TRY(hipEventRecord(te.t0, b->stream));
     if (graph)
         HIP_TRY(hipGraphLaunch(b->step_graph[par], b->stream));
     else
         for (int64_t st = 0; st < s_eff; ++st) HIP_TRY(one_step());
+    if (te.t1) HIP_TRY(hipEventRecord(te.t1, b->stream));
     // requests finished by this tick: their FP64 sums go to pinned memory
     for (int k : act) {
         Slot& sl = b->slots[k];
@@ -1372,7 +1445,6 @@ int batch_tick(eulbfs_batch* b, int32_t steps)
         HIP_TRY(hipMemcpyAsync(b->h_sums + (size_t)k * NRED, dout, NRED * sizeof(double), hipMemcpyDeviceToHost,
                                b->stream));
     }
-    TickEvent te;
     HIP_TRY(hipEventCreateWithFlags(&te.ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(te.ev, b->stream));
     te.tick = b->tick;
@@ -1447,8 +1519,11 @@ int eulbfs_batch_create(size_t hbm_budget, int32_t max_slots, int32_t precision,
     b->stream = (hipStream_t)hip_stream;
     b->slots.resize(max_slots);
     b->desc_bytes = align_up((size_t)max_slots * desc_size(precision));
-    // a tile holds BATCH_TX * BATCH_TY cells of at least 88 bytes (three FP32-mode copies of W + dF_s/dt)
-    b->tile_cap = max_slots + (int)std::min<size_t>(hbm_budget / ((size_t)BATCH_TX * BATCH_TY * 88), 1 << 26);
+    // a whole tile holds 512 cells (either shape) of at least 88 bytes (three
+    // FP32-mode copies of W + dF_s/dt); partial tiles at the grids' edges get
+    // as much again
+    static_assert(BATCH_TX[0] * BATCH_TY[0] == 512 && BATCH_TX[1] * BATCH_TY[1] == 512, "512-cell batch tiles");
+    b->tile_cap = 2 * (max_slots + (int)std::min<size_t>(hbm_budget / ((size_t)512 * 88), 1 << 25));
     const size_t tiles_bytes = align_up((size_t)b->tile_cap * sizeof(int));
     const size_t tables = 2 * (b->desc_bytes + tiles_bytes);
     if (hbm_budget <= tables) {
@@ -1612,6 +1687,32 @@ int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot)
     return EULBFS_OK;
 }
 
+int eulbfs_batch_set_tile(eulbfs_batch_t b, int32_t tile)
+{
+    if (!b) return set_err(nullptr, EULBFS_EINVAL, "batch is NULL");
+    if (tile < EULBFS_BATCH_TILE_AUTO || tile > NBATCH_TILES)
+        return set_err(&b->err, EULBFS_EINVAL, "unknown batch tile");
+    b->tile_mode = tile;
+    return EULBFS_OK;
+}
+
+int eulbfs_batch_schedule(eulbfs_batch_t b, eulbfs_batch_sched* out)
+{
+    static_assert(NBATCH_TILES == 2 && EULBFS_BATCH_TILE_64x8 == NBATCH_TILES, "the header's two batch tiles");
+    if (!b) return set_err(nullptr, EULBFS_EINVAL, "batch is NULL");
+    if (!out) return set_err(&b->err, EULBFS_EINVAL, "out is NULL");
+    batch_progress(b, false);
+    *out = eulbfs_batch_sched{};
+    out->next_tile = batch_pick_tile(b) + 1;
+    for (int k = 0; k < NBATCH_TILES; ++k) {
+        out->ns_per_cell_step[k] = b->tile_cells[k] > 0.0 ? 1e6 * b->tile_ms[k] / b->tile_cells[k] : 0.0;
+        out->ticks_timed[k] = b->tile_ticks[k];
+    }
+    out->time_ratio = b->pairs ? std::exp(b->log_ratio) : 0.0;
+    out->pairs = b->pairs;
+    return EULBFS_OK;
+}
+
 int eulbfs_batch_destroy(eulbfs_batch_t b)
 {
     if (!b) return EULBFS_OK;
@@ -1619,7 +1720,11 @@ int eulbfs_batch_destroy(eulbfs_batch_t b)
     if (b->upload) (void)hipStreamSynchronize(b->upload);
     for (auto& sl : b->slots)
         if (sl.s) free_solver(sl.s, false);
-    for (auto& te : b->events) (void)hipEventDestroy(te.ev);
+    for (auto& te : b->events) {
+        (void)hipEventDestroy(te.ev);
+        if (te.t0) (void)hipEventDestroy(te.t0);
+        if (te.t1) (void)hipEventDestroy(te.t1);
+    }
     if (b->h_sums) (void)hipHostFree(b->h_sums);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->stage_done) (void)hipEventDestroy(b->stage_done);

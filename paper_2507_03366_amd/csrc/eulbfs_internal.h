@@ -30,10 +30,12 @@ enum { TILE_32x8 = 0, TILE_64x4 = 1, TILE_16x16 = 2, TILE_64x8 = 3, TILE_32x16 =
 
 constexpr int NXCD = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
-// Tile of the batched stage kernel: for the serving mix (grids of 64^2 to 512^2
-// in FP32 mode) 32 x 16 beat 32 x 8, 64 x 8 and 32 x 32 (67, 60, 66 and 48
-// solves/s).
-constexpr int BATCH_TX = 32, BATCH_TY = 16;
+// Tiles of the batched stage kernel: the two shapes that led on the serving
+// mix (grids of 64^2 to 512^2 in FP32 mode: 67 and 66 solves/s against 60 for
+// 32 x 8 and 48 for 32 x 32).  A batch picks one of them by timing its own
+// ticks; stretched meshes always take the first.
+constexpr int NBATCH_TILES = 2;
+constexpr int BATCH_TX[NBATCH_TILES] = {32, 64}, BATCH_TY[NBATCH_TILES] = {16, 8};
 
 // Tile of the fused stage kernel on a stretched mesh, one shape per field
 // type: 32 x 16 in FP64, where a 1024-thread 32 x 32 tile would need 162 KB of
@@ -82,7 +84,7 @@ hipError_t launch_export(const DevParams& P, const State<R>& S, const R* fsdot, 
                          hipStream_t st);
 template <typename R>
 hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
-                                bool nu, const StageCoef& K, int stage, hipStream_t st);
+                                bool nu, int tile, const StageCoef& K, int stage, hipStream_t st);
 template <typename R>
 hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial, int nblocks, double* out,
                          hipStream_t st);

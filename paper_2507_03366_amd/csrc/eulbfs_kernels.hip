@@ -930,49 +930,58 @@ hipError_t launch_stage_fused(const DevParams& P, int tile, const StageCoef& K, 
     return launch_fused_l<R, 9>(P, tile, K, in, Wn, out, fsdot, st);
 }
 
-template <typename R, int LAT, int FAST, bool NU = false>
+template <typename R, int LAT, int FAST, int TB, bool NU = false>
 static void launch_batched_t(const BatchDesc<R>* descs, const int* tile_req, int ntiles, const StageCoef& K,
                              int stage, hipStream_t st)
 {
+    constexpr int TX = BATCH_TX[TB], TY = BATCH_TY[TB];
     const int per_xcd = (ntiles + NXCD - 1) / NXCD;
-    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, BATCH_TX, BATCH_TY, NU>), dim3(per_xcd * NXCD),
-                       dim3(BATCH_TX * BATCH_TY), 0, st, descs, tile_req, ntiles, K, stage);
+    hipLaunchKernelGGL((k_stage_batched<R, LAT, FAST, TX, TY, NU>), dim3(per_xcd * NXCD), dim3(TX * TY), 0, st,
+                       descs, tile_req, ntiles, K, stage);
+}
+
+template <typename R, int LAT, int TB>
+static void launch_batched_f(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int f, const StageCoef& K,
+                             int stage, hipStream_t st)
+{
+    switch (f) {
+        case FAST_HALF: launch_batched_t<R, LAT, FAST_HALF, TB>(descs, tile_req, ntiles, K, stage, st); break;
+        case FAST_UCP: launch_batched_t<R, LAT, FAST_UCP, TB>(descs, tile_req, ntiles, K, stage, st); break;
+        case FAST_HALF | FAST_UCP:
+            launch_batched_t<R, LAT, FAST_HALF | FAST_UCP, TB>(descs, tile_req, ntiles, K, stage, st);
+            break;
+        default: launch_batched_t<R, LAT, 0, TB>(descs, tile_req, ntiles, K, stage, st); break;
+    }
 }
 
 // Requests of one batched launch share the mesh kind, the lattice and the
-// fast-path flags (a stretched mesh never has FAST_HALF).
+// fast-path flags (a stretched mesh never has FAST_HALF); tile indexes
+// BATCH_TX/BATCH_TY and is the one their tile list was built for (stretched
+// meshes: always 0).
 template <typename R>
 hipError_t launch_stage_batched(const BatchDesc<R>* descs, const int* tile_req, int ntiles, int lattice, int fast,
-                                bool nu, const StageCoef& K, int stage, hipStream_t st)
+                                bool nu, int tile, const StageCoef& K, int stage, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     const int f = fast & (FAST_HALF | FAST_UCP);
     if (nu) {
         const bool ucp = (f & FAST_UCP) != 0;
         if (lattice == 5) {
-            if (ucp) launch_batched_t<R, 5, FAST_UCP, true>(descs, tile_req, ntiles, K, stage, st);
-            else launch_batched_t<R, 5, 0, true>(descs, tile_req, ntiles, K, stage, st);
+            if (ucp) launch_batched_t<R, 5, FAST_UCP, 0, true>(descs, tile_req, ntiles, K, stage, st);
+            else launch_batched_t<R, 5, 0, 0, true>(descs, tile_req, ntiles, K, stage, st);
         } else {
-            if (ucp) launch_batched_t<R, 9, FAST_UCP, true>(descs, tile_req, ntiles, K, stage, st);
-            else launch_batched_t<R, 9, 0, true>(descs, tile_req, ntiles, K, stage, st);
+            if (ucp) launch_batched_t<R, 9, FAST_UCP, 0, true>(descs, tile_req, ntiles, K, stage, st);
+            else launch_batched_t<R, 9, 0, 0, true>(descs, tile_req, ntiles, K, stage, st);
         }
         return hipGetLastError();
     }
-#define EULBFS_BATCHED(LATV)                                                                                    \
-    switch (f) {                                                                                                \
-        case FAST_HALF: launch_batched_t<R, LATV, FAST_HALF>(descs, tile_req, ntiles, K, stage, st); break;      \
-        case FAST_UCP: launch_batched_t<R, LATV, FAST_UCP>(descs, tile_req, ntiles, K, stage, st); break;        \
-        case FAST_HALF | FAST_UCP:                                                                              \
-            launch_batched_t<R, LATV, FAST_HALF | FAST_UCP>(descs, tile_req, ntiles, K, stage, st);              \
-            break;                                                                                              \
-        default: launch_batched_t<R, LATV, 0>(descs, tile_req, ntiles, K, stage, st); break;                     \
-    }
     if (lattice == 5) {
-        EULBFS_BATCHED(5)
+        if (tile == 1) launch_batched_f<R, 5, 1>(descs, tile_req, ntiles, f, K, stage, st);
+        else launch_batched_f<R, 5, 0>(descs, tile_req, ntiles, f, K, stage, st);
     } else {
-        EULBFS_BATCHED(9)
+        if (tile == 1) launch_batched_f<R, 9, 1>(descs, tile_req, ntiles, f, K, stage, st);
+        else launch_batched_f<R, 9, 0>(descs, tile_req, ntiles, f, K, stage, st);
     }
-#undef EULBFS_BATCHED
     return hipGetLastError();
 }
 
@@ -1058,7 +1067,7 @@ hipError_t launch_reduce(const DevParams& P, const State<R>& S, double* partial,
                                                 hipStream_t);                                                      \
     template hipError_t launch_export<R>(const DevParams&, const State<R>&, const R*, int, double*, hipStream_t);  \
     template hipError_t launch_reduce<R>(const DevParams&, const State<R>&, double*, int, double*, hipStream_t);   \
-    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, bool,              \
+    template hipError_t launch_stage_batched<R>(const BatchDesc<R>*, const int*, int, int, int, bool, int,         \
                                                 const StageCoef&, int, hipStream_t);
 
 EULBFS_INSTANTIATE(double)

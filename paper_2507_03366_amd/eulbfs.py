@@ -331,8 +331,11 @@ def _batch_lib():
         L.eulbfs_batch_destroy.argtypes = [vp]
         L.eulbfs_batch_last_error.argtypes = [vp]
         L.eulbfs_batch_last_error.restype = ct.c_char_p
+        L.eulbfs_batch_set_tile.argtypes = [vp, ct.c_int32]
+        L.eulbfs_batch_schedule.argtypes = [vp, ct.POINTER(eulbfs_batch_sched)]
         for f in ("eulbfs_batch_create", "eulbfs_batch_admit", "eulbfs_batch_tick", "eulbfs_batch_poll",
-                  "eulbfs_batch_query", "eulbfs_batch_release", "eulbfs_batch_destroy"):
+                  "eulbfs_batch_query", "eulbfs_batch_release", "eulbfs_batch_destroy", "eulbfs_batch_set_tile",
+                  "eulbfs_batch_schedule"):
             getattr(L, f).restype = ct.c_int
         L._batch_ready = True
     return L
@@ -394,6 +397,29 @@ def eulbfs_batch_query(b, slot: int, what: int, nx: int, ny: int) -> np.ndarray:
     return out
 
 
+BATCH_TILE_AUTO, BATCH_TILE_32x16, BATCH_TILE_64x8 = 0, 1, 2
+BATCH_TILE_NAMES = {BATCH_TILE_32x16: "32x16", BATCH_TILE_64x8: "64x8"}
+
+
+class eulbfs_batch_sched(ct.Structure):
+    _fields_ = [("next_tile", ct.c_int32), ("reserved", ct.c_int32), ("ns_per_cell_step", ct.c_double * 2),
+                ("ticks_timed", ct.c_int64 * 2), ("time_ratio", ct.c_double), ("pairs", ct.c_int64)]
+
+
+def eulbfs_batch_set_tile(b, tile: int) -> None:
+    _braise(_batch_lib().eulbfs_batch_set_tile(b, int(tile)), b)
+
+
+def eulbfs_batch_schedule(b) -> dict:
+    """What the batch's tile choice has measured: the next tick's tile, device
+    ns per cell-step and timed ticks of each shape, the paired time ratio
+    64x8 / 32x16 and the number of pairs."""
+    s = eulbfs_batch_sched()
+    _braise(_batch_lib().eulbfs_batch_schedule(b, ct.byref(s)), b)
+    return {"next_tile": s.next_tile, "ns_per_cell_step": [s.ns_per_cell_step[0], s.ns_per_cell_step[1]],
+            "ticks_timed": [s.ticks_timed[0], s.ticks_timed[1]], "time_ratio": s.time_ratio, "pairs": s.pairs}
+
+
 def eulbfs_batch_release(b, slot: int) -> None:
     _braise(_batch_lib().eulbfs_batch_release(b, slot), b)
 
@@ -443,6 +469,12 @@ class Batch:
     def diagnostics(self, slot: int) -> dict:
         nx, ny = self.shapes[slot]
         return dict(zip(DIAG_NAMES, eulbfs_batch_query(self.b, slot, SCALAR_DIAG, nx, ny)))
+
+    def set_tile(self, tile: int):
+        eulbfs_batch_set_tile(self.b, tile)
+
+    def schedule(self):
+        return eulbfs_batch_schedule(self.b)
 
     def release(self, slot: int):
         eulbfs_batch_release(self.b, slot)

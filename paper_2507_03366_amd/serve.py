@@ -83,9 +83,11 @@ def percentiles(lat):
 
 
 def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int = 2 << 30, max_slots: int = 64,
-          tick_steps: int = 100, stream=None) -> dict:
+          tick_steps: int = 100, stream=None, tile: int = E.BATCH_TILE_AUTO) -> dict:
     """Run the requests through one batch; arrival times are in seconds from
-    the start (requests[k].arrival).  Returns throughput and latency stats."""
+    the start (requests[k].arrival).  Returns throughput and latency stats and
+    the batch's tile choice (its measured device time per cell-step of each
+    shape)."""
     import torch
 
     if stream is None:
@@ -94,6 +96,7 @@ def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int =
         if r.problem is None:
             r.problem, r.state = build(r, precision)
     batch = E.Batch(hbm_budget, max_slots, precision=precision, stream=stream)
+    batch.set_tile(tile)
     waiting = sorted(requests, key=lambda r: r.arrival)
     resident = {}  # slot -> request
     finish = {}
@@ -140,6 +143,7 @@ def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int =
                     enqueued.pop(slot, None)
             elif waiting:
                 time.sleep(max(0.0, min(waiting[0].arrival - now, 0.05)))
+        sched = batch.schedule()
     finally:
         batch.close()
     total = time.perf_counter() - t0
@@ -150,7 +154,14 @@ def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int =
             "p50_s": p50, "p99_s": p99, "mean_s": float(np.mean(lat)), "ticks": ticks,
             "cell_updates_per_s": cells / total, "failed": failed,
             "precision": "fp32" if precision == E.FP32 else "fp64", "tick_steps": tick_steps,
-            "hbm_budget": hbm_budget, "max_slots": max_slots}
+            "hbm_budget": hbm_budget, "max_slots": max_slots,
+            "tile": {"mode": "auto" if tile == E.BATCH_TILE_AUTO else E.BATCH_TILE_NAMES[tile],
+                     "next": E.BATCH_TILE_NAMES[sched["next_tile"]],
+                     "ns_per_cell_step": {E.BATCH_TILE_NAMES[k + 1]: round(sched["ns_per_cell_step"][k], 5)
+                                          for k in range(2)},
+                     "ticks_timed": {E.BATCH_TILE_NAMES[k + 1]: sched["ticks_timed"][k] for k in range(2)},
+                     "paired_time_ratio_64x8_over_32x16": round(sched["time_ratio"], 4),
+                     "pairs": sched["pairs"]}}
 
 
 def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None) -> dict:
@@ -247,12 +258,20 @@ def accuracy(requests: List[Request], *, max_slots: int = 64, hbm_budget: int = 
 
 def run_mix(count: int = 256, nsteps: int = 2000, seed: int = 0, load: float = 0.8, hbm_budget: int = 2 << 30,
             max_slots: int = 64, tick_steps: int = 100, sizes=SIZES, with_sequential: bool = True,
-            accuracy_requests: int = 24) -> dict:
+            accuracy_requests: int = 24, compare_tiles: bool = True) -> dict:
     """The serving benchmark: (1) all requests at t = 0 through the batched
-    FP32 server (capacity), (2) Poisson arrivals at `load` times that capacity
-    (latency under load), (3) the sequential FP64 baseline on the burst."""
+    FP32 server (capacity) with the tile chosen on the fly, and (with
+    compare_tiles) again with each tile shape pinned, (2) Poisson arrivals at
+    `load` times that capacity (latency under load), (3) the sequential FP64
+    baseline on the burst."""
     reqs = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
     burst = serve(reqs, hbm_budget=hbm_budget, max_slots=max_slots, tick_steps=tick_steps)
+    pinned = {}
+    if compare_tiles:
+        for tile, name in E.BATCH_TILE_NAMES.items():
+            rp = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
+            pinned[name] = round(serve(rp, hbm_budget=hbm_budget, max_slots=max_slots, tick_steps=tick_steps,
+                                       tile=tile)["solves_per_s"], 2)
     rate = load * burst["solves_per_s"]
     arr = poisson_arrivals(count, rate, seed=seed + 1)
     reqs2 = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
@@ -261,6 +280,8 @@ def run_mix(count: int = 256, nsteps: int = 2000, seed: int = 0, load: float = 0
     loaded = serve(reqs2, hbm_budget=hbm_budget, max_slots=max_slots, tick_steps=tick_steps)
     out = {"requests": count, "steps_per_request": nsteps, "seed": seed, "batched_fp32_burst": burst,
            "batched_fp32_poisson": dict(loaded, arrival_rate_per_s=rate, load=load)}
+    if pinned:
+        out["batched_fp32_burst_pinned_tile_solves_per_s"] = pinned
     if with_sequential:
         reqs3 = draw_requests(count, seed=seed, nsteps=nsteps, sizes=sizes)
         out["sequential_fp64_burst"] = sequential(reqs3)

@@ -37,6 +37,8 @@ def test_bench_json_line():
     if rl["frac"] is not None:
         assert 0 < rl["frac"] < 1 and 0 < rl["valu_issue_frac"] < 1
     assert d["serving"]["batched_fp32_burst"]["failed"] == []
+    assert set(d["serving"]["batched_fp32_burst_pinned_tile_solves_per_s"]) == {"32x16", "64x8"}
+    assert d["serving"]["batched_fp32_burst"]["tile"]["mode"] == "auto"
     acc = d["serving"]["accuracy_fp32_vs_fp64"]
     assert acc["requests"] == 6 and acc["within_bar"], acc
     cb = d["cpu_baseline"]

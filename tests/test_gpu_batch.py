@@ -38,11 +38,12 @@ def _requests():
     return reqs
 
 
-def _run_batch(reqs, nsteps, precision=E.FP64, tick=10, budget=1 << 28):
+def _run_batch(reqs, nsteps, precision=E.FP64, tick=10, budget=1 << 28, tile=E.BATCH_TILE_AUTO, schedule=None):
     import torch
 
     b = E.Batch(budget, 16, precision=precision, stream=torch.cuda.Stream())
     try:
+        b.set_tile(tile)
         slots = [b.admit(pr, st, n) for (pr, st), n in zip(reqs, nsteps)]
         assert all(s is not None for s in slots)
         while True:
@@ -55,6 +56,8 @@ def _run_batch(reqs, nsteps, precision=E.FP64, tick=10, budget=1 << 28):
         assert done == set(slots)
         out = [b.conserved(s) for s in slots]
         diags = [b.diagnostics(s) for s in slots]
+        if schedule is not None:
+            schedule.append(b.schedule())
         for s in slots:
             b.release(s)
     finally:
@@ -204,3 +207,55 @@ def test_batch_step_graphs_match_eager_ticks():
     assert len(captured) == len(eager)
     for x, y in zip(captured, eager):
         assert np.array_equal(x, y)
+
+
+def _graded_request():
+    wx = PB.graded_widths(60, 0.6, 1.04, 1.5, both_ends=True)
+    wy = PB.graded_widths(45, 0.6, 1.05, 1.5)
+    pr = PB.Problem(nx=60, ny=45, x_width=wx, y_width=wy, rho=(0.917, 1.0, 0.01), mu=(0.05, 0.05, 0.0005),
+                    lam=(0.4, 0.4, 0.004), latent=10.0, sigma=0.005, gy=-1e-5, delta_t=0.3, dt=0.3,
+                    walls={"y-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -1.0, 75.0), "y+": PB.Wall(PB.FREESLIP),
+                           "x-": PB.Wall(), "x+": PB.Wall()})
+    X, Y = PB.cell_centres(pr)
+    st = PB.uniform_state(pr, T0=0.1)
+    st.C = PB.droplet_profile(X, Y, 0.5 * wx.sum(), 0.0, 15.0, pr.xi)
+    return pr, st
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.FP32])
+def test_batch_tile_shapes_give_the_same_bits(precision):
+    """The uneven mix plus a stretched request with the batch tile pinned to
+    32x16, pinned to 64x8 and chosen on the fly: every request bitwise the same.
+    After ten ticks the automatic choice has timed both shapes on back-to-back
+    ticks of the same work."""
+    reqs = _requests() + [_graded_request()]
+    nsteps = [100, 80, 100, 60, 100, 90]
+    a, _ = _run_batch(reqs, nsteps, precision=precision, tile=E.BATCH_TILE_32x16)
+    b, _ = _run_batch(reqs, nsteps, precision=precision, tile=E.BATCH_TILE_64x8)
+    sched = []
+    c, _ = _run_batch(reqs, nsteps, precision=precision, tile=E.BATCH_TILE_AUTO, schedule=sched)
+    for k in range(len(reqs)):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+    sc = sched[0]
+    assert min(sc["ticks_timed"]) >= 1 and min(sc["ns_per_cell_step"]) > 0
+    assert sc["pairs"] >= 1 and sc["time_ratio"] > 0
+    assert sc["next_tile"] in (E.BATCH_TILE_32x16, E.BATCH_TILE_64x8)
+
+
+def test_batch_tile_choice_rejects_unknown_values():
+    import torch
+
+    b = E.Batch(1 << 26, 2, precision=E.FP32, stream=torch.cuda.Stream())
+    try:
+        for bad in (-1, 3):
+            with pytest.raises(E.EulbfsError) as ei:
+                b.set_tile(bad)
+            assert ei.value.code == E.EINVAL
+        b.set_tile(E.BATCH_TILE_64x8)
+        assert b.schedule()["next_tile"] == E.BATCH_TILE_64x8
+        b.set_tile(E.BATCH_TILE_AUTO)
+        sc = b.schedule()  # nothing timed yet: tick 0 runs 32x16
+        assert sc["next_tile"] == E.BATCH_TILE_32x16 and sc["pairs"] == 0 and sc["ticks_timed"] == [0, 0]
+    finally:
+        b.close()
