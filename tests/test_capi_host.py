@@ -215,3 +215,19 @@ def test_diffusion_radius_matches_the_matrix_eigenvalues():
                       periodic_x=True, walls={"y-": PB.Wall(PB.NOSLIP, PB.DIRICHLET, -1.0), "y+": PB.Wall()})
     assert E.eulbfs_check_params(E.params_from_problem(base.replace(dt=0.999 * dt_lim))) == ""
     assert "thermal" in E.eulbfs_check_params(E.params_from_problem(base.replace(dt=1.001 * dt_lim)))
+
+
+def test_grid_size_limit():
+    """The largest grid the library takes: 2^31 cells are accepted and their
+    workspace is sized without overflow (three FP64 copies of five fields
+    and dF_s/dt alone are 128 B per cell); one row more is rejected.  A row
+    or column below 4 cells is rejected as well."""
+    P = _params(nx=65536, ny=32768)
+    assert E.eulbfs_check_params(P) == ""
+    assert E.eulbfs_workspace_bytes(P) >= (1 << 31) * 128
+    assert "too large" in E.eulbfs_check_params(_params(nx=65536, ny=32769))
+    assert "nx and ny" in E.eulbfs_check_params(_params(ny=3))
+    P32 = E.params_from_problem(PB.static_droplet(n=64, R=16, sigma=0.015625)[0].replace(nx=65536, ny=32768),
+                                precision=E.FP32)
+    assert E.eulbfs_check_params(P32) == ""
+    assert 0 < E.eulbfs_workspace_bytes(P32) < E.eulbfs_workspace_bytes(P)
