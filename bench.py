@@ -45,20 +45,20 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_internal.h, csrc/eulbfs_kernels.hip and
 # build.py).
-COUNTS_FINGERPRINT = "8a9533d20a40ca69"
+COUNTS_FINGERPRINT = "d5936c78371c7fba"
 COUNTS = {
-    "fp64/32x8": {"f64": 1237.2, "valu": 1197.9, "hbm": 31888967},
-    "fp64/64x4": {"f64": 1257.8, "valu": 1243.6, "hbm": 31885639},
-    "fp64/16x16": {"f64": 1237.6, "valu": 1190.9, "hbm": 31876426},
-    "fp64/64x8": {"f64": 1128.2, "valu": 1104.1, "hbm": 31867464},
-    "fp64/32x16": {"f64": 1122.8, "valu": 1088.6, "hbm": 31877703},
-    "fp64/32x32": {"f64": 1110.9, "valu": 1076.2, "hbm": 31913080},
-    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1228.9, "hbm": 21815187},
-    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1276.4, "hbm": 21829794},
-    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1219.0, "hbm": 22476400},
-    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1125.3, "hbm": 21810621},
-    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1107.5, "hbm": 21803578},
-    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1053.6, "hbm": 21830552},
+    "fp64/32x8": {"f64": 1237.2, "valu": 1197.9, "hbm": 31890633},
+    "fp64/64x4": {"f64": 1257.8, "valu": 1243.6, "hbm": 31892297},
+    "fp64/16x16": {"f64": 1237.6, "valu": 1190.9, "hbm": 31875401},
+    "fp64/64x8": {"f64": 1128.2, "valu": 1104.1, "hbm": 31878729},
+    "fp64/32x16": {"f64": 1122.8, "valu": 1088.6, "hbm": 31862345},
+    "fp64/32x32": {"f64": 1110.9, "valu": 1076.2, "hbm": 31901572},
+    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1228.9, "hbm": 21815682},
+    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1276.4, "hbm": 21829784},
+    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1219.0, "hbm": 22431550},
+    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1125.3, "hbm": 21814845},
+    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1107.5, "hbm": 21797285},
+    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1053.6, "hbm": 21835461},
 }
 # an FP64 VALU instruction of a wave64 occupies its 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second.  Other VALU
@@ -157,10 +157,12 @@ def oracle_rate(pr, st, budget_s: float, threads: int):
     W = O.init(pr, st)
     fs = np.zeros((pr.ny, pr.nx))
     t0 = time.perf_counter()
-    W, fs = O.step(pr, W, fs, 1)
+    W, fs = O.step(pr, W, fs, 1)  # the first step also starts the thread pool
     t1 = time.perf_counter()
-    steps = 1
-    more = int(max(0.0, budget_s - (t1 - t0)) / max(t1 - t0, 1e-6))
+    W, fs = O.step(pr, W, fs, 1)
+    t2 = time.perf_counter()
+    steps = 2
+    more = int(max(0.0, budget_s - (t2 - t0)) / max(t2 - t1, 1e-6))
     if more > 0:
         W, fs = O.step(pr, W, fs, more)
         steps += more
@@ -229,6 +231,7 @@ def hbm_batch_point(count: int, n: int, steps: int):
     need = E.eulbfs_batch_request_bytes(E.params_from_problem(pr, precision=E.FP32))
     stream = torch.cuda.Stream()
     b = E.Batch(need * count + (64 << 20), count, precision=E.FP32, stream=stream)
+    b.set_tile(E.BATCH_TILE_32x16)  # the shape a batch settles on for the serving mix
     try:
         for _ in range(count):
             assert b.admit(pr, st, 2 * steps + 8) is not None
