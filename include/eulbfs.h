@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define EULBFS_ABI_VERSION 5u
+#define EULBFS_ABI_VERSION 6u
 
 /* status codes */
 #define EULBFS_OK 0
@@ -178,10 +178,44 @@ typedef struct {
 /* Initial state. */
 #define EULBFS_INIT_PRIMITIVE 0 /* 6 planes: T, F_l, C, u, v, p                */
 #define EULBFS_INIT_CONSERVED 1 /* 6 planes: H, p, Mx, My, C, dF_s/dt (restart) */
+#define EULBFS_INIT_ANALYTIC 2  /* the closed-form fields of *shape, built on the
+                                   device; planes and on_device are not read   */
+
+/* Closed-form initial fields (EULBFS_INIT_ANALYTIC).  With cell centres x_i,
+ * y_j ((i + 1/2) dx on a uniform mesh, the running sums of the widths on a
+ * stretched one):
+ *   C    UNIFORM: c0.  LAYER: the flat interface of Eq. (61) at s = h0,
+ *        (1 + tanh(2 (h0 - s) / xi)) / 2 with s = x_i (axis 0) or y_j (axis 1).
+ *        DROPLET: the circle of Eq. (62) (with the distance to the centre),
+ *        (1 + tanh(2 (r0 - r) / xi)) / 2, r = sqrt((x_i - x0)^2 + (y_j - y0)^2).
+ *   T    t_in where C > 1/2, else t_out; plus t_amp times a number uniform in
+ *        [-1, 1) drawn for cell n = j nx + i by the splitmix64 generator (state
+ *        seed + (n + 1) 0x9E3779B97F4A7C15, its output mix, top 53 bits) when
+ *        t_amp is not 0.
+ *   F_l  fl0.   u, v  u_in C, v_in C (0 where u_in, v_in are 0).   p  0.
+ * These primitive fields then take the EULBFS_INIT_PRIMITIVE path. */
+#define EULBFS_PROFILE_UNIFORM 0
+#define EULBFS_PROFILE_LAYER 1
+#define EULBFS_PROFILE_DROPLET 2
+typedef struct {
+    int32_t profile;      /* EULBFS_PROFILE_*                            */
+    int32_t axis;         /* LAYER: 0 across x, 1 across y               */
+    double c0;            /* UNIFORM: C                                  */
+    double h0;            /* LAYER: position of C = 1/2                  */
+    double x0, y0, r0;    /* DROPLET: centre and radius                  */
+    double t_out, t_in;   /* T where C <= 1/2 and where C > 1/2          */
+    double t_amp;         /* amplitude of the seeded temperature noise   */
+    uint64_t seed;
+    double fl0;           /* F_l                                         */
+    double u_in, v_in;    /* velocity per unit C                         */
+} eulbfs_shape;
+
 typedef struct {
     int32_t kind;
-    int32_t on_device;   /* 1: planes point to device memory             */
+    int32_t on_device;    /* 1: planes point to device memory             */
     const double* planes; /* 6 * nx * ny doubles, plane after plane       */
+    const eulbfs_shape* shape; /* EULBFS_INIT_ANALYTIC: host memory, read
+                                  before the call returns              */
 } eulbfs_init;
 /* EULBFS_INIT_PRIMITIVE: H = (1 - F_l)(H_s + C_p^S (T - T_s)) + F_l (H_l +
  * C_p^L (T - T_l)) with H_s = C_p^S T_s, H_l = C_p^L T_l + L (so a liquid

@@ -593,9 +593,30 @@ int enqueue_steps(eulbfs_solver* h, int64_t n)
     return EULBFS_OK;
 }
 
-// Initial state from six planes.  With sync = false nothing waits: host planes
-// must stay valid until the stream has run the copy (batch admission passes
-// planes already on the device).
+// What is wrong with an initial-state description, or "".
+std::string init_error(const eulbfs_init* init)
+{
+    if (!init) return "init is NULL";
+    if (init->kind == EULBFS_INIT_ANALYTIC) {
+        const eulbfs_shape* e = init->shape;
+        if (!e) return "init->shape is NULL";
+        if (e->profile < EULBFS_PROFILE_UNIFORM || e->profile > EULBFS_PROFILE_DROPLET) return "unknown shape profile";
+        if (e->profile == EULBFS_PROFILE_LAYER && e->axis != 0 && e->axis != 1) return "layer axis must be 0 or 1";
+        const double v[] = {e->c0, e->h0, e->x0, e->y0, e->r0, e->t_out, e->t_in, e->t_amp, e->fl0, e->u_in, e->v_in};
+        for (double x : v)
+            if (!std::isfinite(x)) return "shape values must be finite";
+        if (e->fl0 < 0.0 || e->fl0 > 1.0) return "shape fl0 must be in [0, 1]";
+        return "";
+    }
+    if (init->kind != EULBFS_INIT_PRIMITIVE && init->kind != EULBFS_INIT_CONSERVED) return "unknown init kind";
+    if (!init->planes) return "init->planes is NULL";
+    return "";
+}
+
+// Initial state from six planes or a closed-form shape.  With sync = false
+// nothing waits: host planes must stay valid until the stream has run the
+// copy (batch admission passes planes already on the device); a shape is
+// read before the call returns.
 template <typename R>
 int do_init(eulbfs_solver* h, const eulbfs_init* init, bool sync = true)
 {
@@ -604,13 +625,19 @@ int do_init(eulbfs_solver* h, const eulbfs_init* init, bool sync = true)
     const size_t n6 = (size_t)6 * h->prm.nx * h->prm.ny;
     double* stage = (double*)(h->ws + L.staging);
     const double* src = init->planes;
-    if (!init->on_device) {
+    if (init->kind == EULBFS_INIT_ANALYTIC) {
+        const eulbfs_shape& e = *init->shape;
+        const InitShape S{e.profile, e.axis, e.c0,    e.h0,   e.x0, e.y0, e.r0, e.t_out,
+                          e.t_in,    e.t_amp, e.seed, e.fl0, e.u_in, e.v_in, h->prm.xi};
+        HIP_TRY(launch_init_shape(h->dp, S, stage, h->stream));
+        src = stage;
+    } else if (!init->on_device) {
         HIP_TRY(hipMemcpyAsync(stage, init->planes, n6 * 8, hipMemcpyHostToDevice, h->stream));
         src = stage;
     }
     State<R> W0 = state_at<R>(h->ws, L.W0, L);
     R* fsdot = (R*)(h->ws + L.fsdot);
-    if (init->kind == EULBFS_INIT_PRIMITIVE)
+    if (init->kind != EULBFS_INIT_CONSERVED)
         HIP_TRY(launch_init<R>(h->dp, src, W0, fsdot, h->stream));
     else
         HIP_TRY(launch_set_conserved<R>(h->dp, src, W0, fsdot, -1, h->stream));
@@ -916,9 +943,8 @@ int create_solver(const eulbfs_params* prm, const eulbfs_init* init, void* d_ws,
     *out = nullptr;
     const std::string e = check(prm);
     if (!e.empty()) return set_err(err, EULBFS_EINVAL, e);
-    if (!init || !init->planes) return set_err(err, EULBFS_EINVAL, "init or init->planes is NULL");
-    if (init->kind != EULBFS_INIT_PRIMITIVE && init->kind != EULBFS_INIT_CONSERVED)
-        return set_err(err, EULBFS_EINVAL, "unknown init kind");
+    const std::string ie = init_error(init);
+    if (!ie.empty()) return set_err(err, EULBFS_EINVAL, ie);
     const Layout L = make_layout(prm);
     if (d_ws && ws_bytes < L.total) return set_err(err, EULBFS_ENOMEM, "workspace smaller than eulbfs_workspace_bytes()");
     if (d_ws && ((uintptr_t)d_ws % ALIGN) != 0) return set_err(err, EULBFS_EINVAL, "workspace must be 256-byte aligned");
@@ -1586,7 +1612,8 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
     int k = 0;
     while (k < b->max_slots && b->slots[k].s) ++k;
     if (k == b->max_slots) return set_err(err, EULBFS_EBUSY, "no free slot");
-    if (!init || !init->planes) return set_err(err, EULBFS_EINVAL, "init or init->planes is NULL");
+    const std::string ie = init_error(init);
+    if (!ie.empty()) return set_err(err, EULBFS_EINVAL, ie);
     const eulbfs_params p = batch_view(prm);
     const Layout L = make_layout(&p);
     const size_t bytes = align_up(L.total);
@@ -1605,7 +1632,7 @@ int eulbfs_batch_admit(eulbfs_batch_t b, const eulbfs_params* prm, const eulbfs_
         }
     }
     eulbfs_init dinit = *init;
-    if (!init->on_device) {
+    if (init->kind != EULBFS_INIT_ANALYTIC && !init->on_device) {
         const size_t n6 = (size_t)6 * p.nx * p.ny;
         int rc = admit_stage(b, init->planes, n6, b->arena + off + L.staging);
         if (rc != EULBFS_OK) {

@@ -76,6 +76,16 @@ hipError_t launch_stage_split(const DevParams& P, const SplitScratch<R>& X, cons
                               hipStream_t st);
 template <typename R>
 hipError_t launch_init(const DevParams& P, const double* prim6, const State<R>& out, R* fsdot, hipStream_t st);
+
+// Closed-form initial primitive fields (the public eulbfs_shape; profile 0
+// uniform, 1 layer, 2 droplet).
+struct InitShape {
+    int profile, axis;
+    double c0, h0, x0, y0, r0, t_out, t_in, t_amp;
+    uint64_t seed;
+    double fl0, u_in, v_in, xi;
+};
+hipError_t launch_init_shape(const DevParams& P, const InitShape& S, double* prim6, hipStream_t st);
 template <typename R>
 hipError_t launch_set_conserved(const DevParams& P, const double* w6, const State<R>& out, R* fsdot, int which,
                                 hipStream_t st);

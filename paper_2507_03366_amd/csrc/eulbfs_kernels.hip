@@ -671,6 +671,64 @@ __global__ void k_init(DevParams P, const double* prim6, State<R> out, R* fsdot)
     fsdot[q] = R(0);
 }
 
+// The n-th output of the splitmix64 generator with state seed (Steele, Lea
+// and Flood, OOPSLA 2014): state seed + n 0x9E3779B97F4A7C15 through the
+// generator's output mix; the top 53 bits as a number uniform in [-1, 1).
+__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+// Cell centre along one direction, the first face at 0: the running sum of
+// the widths up to and including cell i, in index order, less half the
+// cell's own width.  hw: the tabulated half widths (stretched mesh; twice a
+// half width is the width exactly) or nullptr (every width dx).
+__device__ __forceinline__ double cell_centre(const double* hw, int i, double dx)
+{
+    double c = 0.0;
+    for (int k = 0; k <= i; ++k) c += hw ? 2.0 * hw[k] : dx;
+    return c - (hw ? hw[i] : 0.5 * dx);
+}
+
+// Closed-form primitive fields T, F_l, C, u, v, p (six dense planes).
+__global__ void k_init_shape(DevParams P, InitShape S, double* prim6)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    const size_t n = (size_t)P.nx * P.ny, s = (size_t)j * P.nx + i;
+    const double* hwx = P.mside ? P.mxc + MESH_HW * P.msx + NG : nullptr;
+    const double* hwy = P.mside ? P.myc + MESH_HW * P.msy + NG : nullptr;
+    // one rounding per operation, as the closed forms are written (no fused
+    // multiply-adds across these statements)
+    double C = S.c0;
+    if (S.profile == 1) {
+        const double c = S.axis == 0 ? cell_centre(hwx, i, P.dx) : cell_centre(hwy, j, P.dx);
+        const double d = 2.0 * (S.h0 - c);
+        C = 0.5 * (1.0 + tanh(d / S.xi));
+    } else if (S.profile == 2) {
+        const double dx = cell_centre(hwx, i, P.dx) - S.x0, dy = cell_centre(hwy, j, P.dx) - S.y0;
+        const double dx2 = dx * dx, dy2 = dy * dy;
+        const double d = 2.0 * (S.r0 - sqrt(dx2 + dy2));
+        C = 0.5 * (1.0 + tanh(d / S.xi));
+    }
+    double T = C > 0.5 ? S.t_in : S.t_out;
+    if (S.t_amp != 0.0) {
+        const double noise = S.t_amp * splitmix_uniform(S.seed, (uint64_t)s + 1);
+        T = T + noise;
+    }
+    prim6[s] = T;
+    prim6[n + s] = S.fl0;
+    prim6[2 * n + s] = C;
+    prim6[3 * n + s] = S.u_in != 0.0 ? S.u_in * C : 0.0;
+    prim6[4 * n + s] = S.v_in != 0.0 ? S.v_in * C : 0.0;
+    prim6[5 * n + s] = 0.0;
+}
+
 template <typename R>
 __global__ void k_set_conserved(DevParams P, const double* w6, State<R> out, R* fsdot, int which)
 {
@@ -1021,6 +1079,13 @@ hipError_t launch_init(const DevParams& P, const double* prim6, const State<R>& 
 {
     const dim3 b(64, 4);
     hipLaunchKernelGGL(k_init<R>, grid2(P.nx, P.ny, b), b, 0, st, P, prim6, out, fsdot);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_shape(const DevParams& P, const InitShape& S, double* prim6, hipStream_t st)
+{
+    const dim3 b(64, 4);
+    hipLaunchKernelGGL(k_init_shape, grid2(P.nx, P.ny, b), b, 0, st, P, S, prim6);
     return hipGetLastError();
 }
 

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libeulbfs.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 KERNEL_FUSED, KERNEL_SPLIT, KERNEL_AUTO = 0, 1, 2
-INIT_PRIMITIVE, INIT_CONSERVED = 0, 1
-ABI_VERSION = 5
+INIT_PRIMITIVE, INIT_CONSERVED, INIT_ANALYTIC = 0, 1, 2
+ABI_VERSION = 6
 FIELD = dict(H=0, P=1, MX=2, MY=3, C=4, FSDOT=5, T=6, FL=7, FS=8, RHO=9, U=10, V=11, MUC=12, W_ALL=13,
              W_GHOSTED=14)
 SCALAR_DIAG = 100
@@ -57,8 +57,23 @@ class eulbfs_params(ct.Structure):
     ]
 
 
+class eulbfs_shape(ct.Structure):
+    _fields_ = [("profile", ct.c_int32), ("axis", ct.c_int32), ("c0", ct.c_double), ("h0", ct.c_double),
+                ("x0", ct.c_double), ("y0", ct.c_double), ("r0", ct.c_double), ("t_out", ct.c_double),
+                ("t_in", ct.c_double), ("t_amp", ct.c_double), ("seed", ct.c_uint64), ("fl0", ct.c_double),
+                ("u_in", ct.c_double), ("v_in", ct.c_double)]
+
+
 class eulbfs_init(ct.Structure):
-    _fields_ = [("kind", ct.c_int32), ("on_device", ct.c_int32), ("planes", ct.POINTER(ct.c_double))]
+    _fields_ = [("kind", ct.c_int32), ("on_device", ct.c_int32), ("planes", ct.POINTER(ct.c_double)),
+                ("shape", ct.POINTER(eulbfs_shape))]
+
+
+def shape_struct(sh) -> eulbfs_shape:
+    """An eulbfs_shape from a problems.Shape (field for field)."""
+    return eulbfs_shape(int(sh.profile), int(sh.axis), float(sh.c0), float(sh.h0), float(sh.x0), float(sh.y0),
+                        float(sh.r0), float(sh.t_out), float(sh.t_in), float(sh.t_amp), int(sh.seed), float(sh.fl0),
+                        float(sh.u_in), float(sh.v_in))
 
 
 _lib = None
@@ -157,20 +172,34 @@ def eulbfs_workspace_bytes(P: eulbfs_params) -> int:
     return int(lib().eulbfs_workspace_bytes(ct.byref(P)))
 
 
-def eulbfs_create(P: eulbfs_params, init_planes, kind: int = INIT_PRIMITIVE, workspace=None, stream=None):
-    """init_planes: float64 array of 6 * nx * ny (host numpy or device torch tensor).
-    workspace: a torch uint8 CUDA tensor of >= eulbfs_workspace_bytes(P) (or None).
-    stream: a torch.cuda.Stream (or None: the default stream).  Returns the handle."""
+def _init_of(init_planes, kind: int, shape):
+    """The eulbfs_init for host or device planes, or for a problems.Shape
+    (EULBFS_INIT_ANALYTIC); returns it with the objects it points to."""
     init = eulbfs_init()
+    if shape is not None:
+        sh = shape_struct(shape)
+        init.kind, init.on_device = INIT_ANALYTIC, 0
+        init.shape = ct.pointer(sh)
+        return init, sh
     init.kind = kind
     if isinstance(init_planes, np.ndarray):
         arr = np.ascontiguousarray(init_planes, dtype=np.float64)
         init.on_device = 0
         init.planes = arr.ctypes.data_as(ct.POINTER(ct.c_double))
-    else:
-        assert init_planes.dtype.itemsize == 8 and init_planes.is_contiguous()
-        init.on_device = 1
-        init.planes = ct.cast(ct.c_void_p(init_planes.data_ptr()), ct.POINTER(ct.c_double))
+        return init, arr
+    assert init_planes.dtype.itemsize == 8 and init_planes.is_contiguous()
+    init.on_device = 1
+    init.planes = ct.cast(ct.c_void_p(init_planes.data_ptr()), ct.POINTER(ct.c_double))
+    return init, init_planes
+
+
+def eulbfs_create(P: eulbfs_params, init_planes=None, kind: int = INIT_PRIMITIVE, workspace=None, stream=None,
+                  shape=None):
+    """init_planes: float64 array of 6 * nx * ny (host numpy or device torch tensor);
+    or shape: a problems.Shape whose fields the library builds on the device.
+    workspace: a torch uint8 CUDA tensor of >= eulbfs_workspace_bytes(P) (or None).
+    stream: a torch.cuda.Stream (or None: the default stream).  Returns the handle."""
+    init, _held = _init_of(init_planes, kind, shape)  # _held: what init points to, alive through the call
     ws_ptr = ct.c_void_p(workspace.data_ptr()) if workspace is not None else None
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     st = ct.c_void_p(stream.cuda_stream) if stream is not None else None
@@ -247,7 +276,9 @@ class Solver:
     """One grid on the GPU: workspace in a torch uint8 tensor, work on a torch stream."""
 
     def __init__(self, pr, state=None, *, precision=None, kernel=KERNEL_FUSED, tile=(0, 0), device="cuda:0",
-                 stream=None, conserved=None, own_workspace=True):
+                 stream=None, conserved=None, own_workspace=True, analytic=False):
+        """analytic: build the initial fields on the device from state.shape
+        (EULBFS_INIT_ANALYTIC) instead of copying the host planes."""
         import torch
 
         self.pr = pr
@@ -265,10 +296,15 @@ class Solver:
             ws = self.workspace[off:off + nbytes]
         self.stream = stream
         if conserved is not None:
-            planes, kind = np.ascontiguousarray(conserved, dtype=np.float64).ravel(), INIT_CONSERVED
+            self.h = eulbfs_create(self.P, np.ascontiguousarray(conserved, dtype=np.float64).ravel(),
+                                   kind=INIT_CONSERVED, workspace=ws, stream=stream)
+        elif analytic:
+            if state.shape is None:
+                raise ValueError("this initial state has no closed-form shape")
+            self.h = eulbfs_create(self.P, workspace=ws, stream=stream, shape=state.shape)
         else:
-            planes, kind = np.concatenate([a.ravel() for a in state.planes()]), INIT_PRIMITIVE
-        self.h = eulbfs_create(self.P, planes, kind=kind, workspace=ws, stream=stream)
+            planes = np.concatenate([a.ravel() for a in state.planes()])
+            self.h = eulbfs_create(self.P, planes, kind=INIT_PRIMITIVE, workspace=ws, stream=stream)
 
     def step(self, n: int):
         eulbfs_step(self.h, n)
@@ -361,12 +397,10 @@ def eulbfs_batch_create(hbm_budget: int, max_slots: int, precision: int, workspa
     return b
 
 
-def eulbfs_batch_admit(b, P: eulbfs_params, init_planes: np.ndarray, nsteps: int, kind: int = INIT_PRIMITIVE):
-    """Returns the slot index, or None when the batch is full (EBUSY)."""
-    arr = np.ascontiguousarray(init_planes, dtype=np.float64)
-    init = eulbfs_init()
-    init.kind, init.on_device = kind, 0
-    init.planes = arr.ctypes.data_as(ct.POINTER(ct.c_double))
+def eulbfs_batch_admit(b, P: eulbfs_params, init_planes, nsteps: int, kind: int = INIT_PRIMITIVE, shape=None):
+    """Host planes (or a problems.Shape, built on the device); returns the slot
+    index, or None when the batch is full (EBUSY)."""
+    init, _held = _init_of(init_planes, kind, shape)  # _held: what init points to, alive through the call
     slot = ct.c_int32(-1)
     rc = _batch_lib().eulbfs_batch_admit(b, ct.byref(P), ct.byref(init), int(nsteps), ct.byref(slot))
     if rc == EBUSY:
@@ -448,10 +482,15 @@ class Batch:
                                      stream)
         self.shapes = {}
 
-    def admit(self, pr, state, nsteps: int):
+    def admit(self, pr, state, nsteps: int, analytic: bool = False):
+        """analytic: the device builds the initial fields from state.shape."""
         P = params_from_problem(pr, precision=self.precision)
-        planes = np.concatenate([a.ravel() for a in state.planes()])
-        slot = eulbfs_batch_admit(self.b, P, planes, nsteps)
+        if analytic:
+            if state.shape is None:
+                raise ValueError("this initial state has no closed-form shape")
+            slot = eulbfs_batch_admit(self.b, P, None, nsteps, shape=state.shape)
+        else:
+            slot = eulbfs_batch_admit(self.b, P, np.concatenate([a.ravel() for a in state.planes()]), nsteps)
         if slot is not None:
             self.shapes[slot] = (pr.nx, pr.ny)
         return slot

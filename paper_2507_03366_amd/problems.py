@@ -102,6 +102,9 @@ class InitialState:
     u: np.ndarray
     v: np.ndarray
     p: np.ndarray
+    # the closed-form description these fields were built from, if any (the
+    # library can build the same fields on the device from it)
+    shape: Optional["Shape"] = None
 
     def planes(self):
         return [np.ascontiguousarray(a, dtype=np.float64) for a in (self.T, self.Fl, self.C, self.u, self.v, self.p)]
@@ -151,10 +154,63 @@ def uniform_state(pr: Problem, T0: float = 0.0, Fl0: float = 1.0, C0: float = 1.
     )
 
 
-def counter_uniform(seed: int, shape) -> np.ndarray:
-    """Seeded uniform numbers in [-1, 1), keyed by (seed, j, i)."""
-    rng = np.random.default_rng(np.random.SeedSequence([seed, shape[0], shape[1]]))
-    return rng.uniform(-1.0, 1.0, size=shape)
+def splitmix_uniform(seed: int, n: np.ndarray) -> np.ndarray:
+    """Outputs number n of the splitmix64 generator with state `seed` (Steele,
+    Lea and Flood, OOPSLA 2014: the state advances by 0x9E3779B97F4A7C15 and
+    each output is its mix), the top 53 bits as numbers uniform in [-1, 1)."""
+    with np.errstate(over="ignore"):  # arithmetic modulo 2^64
+        z = np.uint64(seed) + np.asarray(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
+
+
+PROFILE_UNIFORM, PROFILE_LAYER, PROFILE_DROPLET = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Shape:
+    """A closed-form initial state: the condensed phase uniform (c0), below a
+    flat interface (Eq. 61, at h0 across x or y) or inside a circle (Eq. 62,
+    centre (x0, y0), radius r0); T = t_in where C > 1/2, else t_out, plus
+    t_amp times splitmix_uniform(seed, j nx + i + 1); F_l = fl0; velocity
+    (u_in, v_in) C; p = 0."""
+
+    profile: int = PROFILE_UNIFORM
+    axis: int = 0
+    c0: float = 1.0
+    h0: float = 0.0
+    x0: float = 0.0
+    y0: float = 0.0
+    r0: float = 0.0
+    t_out: float = 0.0
+    t_in: float = 0.0
+    t_amp: float = 0.0
+    seed: int = 0
+    fl0: float = 1.0
+    u_in: float = 0.0
+    v_in: float = 0.0
+
+    def state(self, pr: "Problem") -> InitialState:
+        """The fields on the problem's mesh (the host-side twin of the
+        library's analytic initialisation)."""
+        X, Y = cell_centres(pr)
+        if self.profile == PROFILE_LAYER:
+            C = layer_profile(X if self.axis == 0 else Y, self.h0, pr.xi)
+        elif self.profile == PROFILE_DROPLET:
+            C = droplet_profile(X, Y, self.x0, self.y0, self.r0, pr.xi)
+        else:
+            C = np.full((pr.ny, pr.nx), float(self.c0))
+        T = np.where(C > 0.5, float(self.t_in), float(self.t_out))
+        if self.t_amp != 0.0:
+            n = np.arange(1, pr.nx * pr.ny + 1, dtype=np.uint64).reshape(pr.ny, pr.nx)
+            T = T + self.t_amp * splitmix_uniform(self.seed, n)
+        zero = np.zeros((pr.ny, pr.nx))
+        u = self.u_in * C if self.u_in != 0.0 else zero.copy()
+        v = self.v_in * C if self.v_in != 0.0 else zero.copy()
+        return InitialState(T=T, Fl=np.full((pr.ny, pr.nx), float(self.fl0)), C=C, u=u, v=v, p=zero.copy(),
+                            shape=self)
 
 
 def seeded_fields(pr: Problem, seed: int, amp: float = 1.0) -> InitialState:
@@ -216,7 +272,7 @@ def conductive_freezing(nx: int = 128, ny: int = 4, ste: float = 0.1, **kw) -> T
         cp=(1.0, 1.0, 1.0), latent=1.0 / ste, periodic_y=True,
         walls={"x-": Wall(NOSLIP, DIRICHLET, -1.0), "x+": Wall(NOSLIP, ADIABATIC)},
     ).replace(**kw)
-    return pr, uniform_state(pr)
+    return pr, Shape().state(pr)
 
 
 def three_phase_stefan(nx: int = 256, ny: int = 8, H0: float = 128.0, ratio: float = 0.9,
@@ -229,10 +285,7 @@ def three_phase_stefan(nx: int = 256, ny: int = 8, H0: float = 128.0, ratio: flo
         sigma=0.01, periodic_y=True,
         walls={"x-": Wall(NOSLIP, DIRICHLET, -1.0), "x+": Wall(NOSLIP, ADIABATIC)},
     ).replace(**kw)
-    X, _ = cell_centres(pr)
-    st = uniform_state(pr)
-    st.C = layer_profile(X, H0, pr.xi)
-    return pr, st
+    return pr, Shape(profile=PROFILE_LAYER, axis=0, h0=H0).state(pr)
 
 
 def stefan_full_freezing(ratio: float, nx: int = 32, ny: int = 1, H0: float = 12.0, ste: float = 0.25,
@@ -254,10 +307,7 @@ def stefan_full_freezing(ratio: float, nx: int = 32, ny: int = 1, H0: float = 12
         sigma=0.01, periodic_y=True,
         walls={"x-": Wall(NOSLIP, DIRICHLET, T_w), "x+": Wall(NOSLIP, ADIABATIC)},
     ).replace(**kw)
-    X, _ = cell_centres(pr)
-    st = uniform_state(pr, T0=T0)
-    st.C = layer_profile(X, H0, pr.xi)
-    return pr, st
+    return pr, Shape(profile=PROFILE_LAYER, axis=0, h0=H0, t_out=T0, t_in=T0).state(pr)
 
 
 def film_freezing(n: int = 256, height: float = 0.3, ratio: float = 0.917, ste: float = 0.05,
@@ -273,11 +323,7 @@ def film_freezing(n: int = 256, height: float = 0.3, ratio: float = 0.917, ste: 
         sigma=sigma, gy=-g,
         walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0), "y+": Wall()},
     ).replace(**kw)
-    _, Y = cell_centres(pr)
-    st = uniform_state(pr)
-    st.C = layer_profile(Y, H0, pr.xi)
-    st.T = amp * counter_uniform(seed, (pr.ny, pr.nx))
-    return pr, st
+    return pr, Shape(profile=PROFILE_LAYER, axis=1, h0=H0, t_amp=amp, seed=seed).state(pr)
 
 
 def static_droplet(n: int = 512, R: float = 128.0, theta_deg: float = 90.0, ratio: float = 0.917,
@@ -294,15 +340,12 @@ def static_droplet(n: int = 512, R: float = 128.0, theta_deg: float = 90.0, rati
         sigma=sigma,
         walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0, theta_deg), "y+": Wall()},
     ).replace(**kw)
-    X, Y = cell_centres(pr)
-    st = uniform_state(pr)
     x0 = 0.5 * pr.nx * pr.dx
     # circular cap of the same area as a half disc of radius R, meeting the wall at theta
     th = math.radians(theta_deg)
     Rc = R * math.sqrt((math.pi / 2.0) / (th - math.sin(th) * math.cos(th)))
     y0 = -Rc * math.cos(th)
-    st.C = droplet_profile(X, Y, x0, y0, Rc, pr.xi)
-    return pr, st
+    return pr, Shape(profile=PROFILE_DROPLET, x0=x0, y0=y0, r0=Rc).state(pr)
 
 
 # Table 3 of the paper (SI units): liquid and solid properties of the two fluids
@@ -347,10 +390,8 @@ def film_table1(ratio: float = 0.917, nx: int = 200, ny: int = 400, H0: float = 
         walls={"x-": Wall(NOSLIP, DIRICHLET, -1.0), "y-": Wall(NOSLIP, DIRICHLET, -1.0),
                "x+": Wall(FREESLIP, ADIABATIC), "y+": Wall(OUTLET, ADIABATIC)},
     ).replace(**kw)
-    _, Y = cell_centres(pr)
-    st = uniform_state(pr, T0=(m["T_0"] - m["T_m"]) / dT)
-    st.C = layer_profile(Y, H0, pr.xi)
-    return pr, st
+    T0 = (m["T_0"] - m["T_m"]) / dT
+    return pr, Shape(profile=PROFILE_LAYER, axis=1, h0=H0, t_out=T0, t_in=T0).state(pr)
 
 
 def table3_droplet(fluid: str, theta_deg: float, ratio: float = None, nx: int = 400, ny: int = 200,
@@ -384,12 +425,9 @@ def table3_droplet(fluid: str, theta_deg: float, ratio: float = None, nx: int = 
         sigma=sigma,
         walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0, theta_deg), "y+": Wall()},
     ).replace(**kw)
-    X, Y = cell_centres(pr)
-    st = uniform_state(pr)
     th = math.radians(theta_deg)
     Rc = R * math.sqrt((math.pi / 2.0) / (th - math.sin(th) * math.cos(th)))
-    st.C = droplet_profile(X, Y, 0.5 * pr.nx * pr.dx, -Rc * math.cos(th), Rc, pr.xi)
-    return pr, st
+    return pr, Shape(profile=PROFILE_DROPLET, x0=0.5 * pr.nx * pr.dx, y0=-Rc * math.cos(th), r0=Rc).state(pr)
 
 
 def impact_droplet(n: int = 256, we: float = 50.0, re: float = 500.0, U: float = 0.05,
@@ -408,14 +446,9 @@ def impact_droplet(n: int = 256, we: float = 50.0, re: float = 500.0, U: float =
         sigma=sigma, mobility=ch_mobility(sigma), surf_model=1,
         walls={"x-": Wall(), "x+": Wall(), "y-": Wall(NOSLIP, DIRICHLET, -1.0, theta_deg), "y+": Wall()},
     ).replace(**kw)
-    X, Y = cell_centres(pr)
-    st = uniform_state(pr)
     x0 = 0.5 * pr.nx * pr.dx
     y0 = 0.5 * D + 2.0 * pr.xi
-    st.C = droplet_profile(X, Y, x0, y0, 0.5 * D, pr.xi)
-    st.T = np.where(st.C > 0.5, -supercool, 0.0)
-    st.v = -U * st.C
-    return pr, st
+    return pr, Shape(profile=PROFILE_DROPLET, x0=x0, y0=y0, r0=0.5 * D, t_in=-supercool, v_in=-U).state(pr)
 
 
 CONFIGS = {

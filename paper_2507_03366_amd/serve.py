@@ -12,7 +12,8 @@ p50/p99 time from arrival to result.
 
 The one-at-a-time baseline runs the same requests in FP64, each on its own
 solver (create with the autotuned tile, run, read the diagnostics, destroy),
-in arrival order.
+in arrival order.  Both build each request's initial fields on the device from
+its closed-form shape (EULBFS_INIT_ANALYTIC).
 """
 from __future__ import annotations
 
@@ -69,6 +70,7 @@ def build(req: Request, precision: int):
         pr, st = PB.static_droplet(n=req.n, R=req.n / 4, theta_deg=d["theta"], ste=d["ste"])
         pr = pr.replace(sigma=STATIC_SIGMA)
         st.T = np.where(st.C > 0.5, -d["supercool"], 0.0)
+        st.shape = dataclasses.replace(st.shape, t_in=-d["supercool"])  # the same state, closed form
     return pr.replace(precision=precision), st
 
 
@@ -111,7 +113,7 @@ def serve(requests: List[Request], *, precision: int = E.FP32, hbm_budget: int =
             # admit arrived requests, first come first served, while they fit
             while waiting and waiting[0].arrival <= now:
                 r = waiting[0]
-                slot = batch.admit(r.problem, r.state, r.nsteps)
+                slot = batch.admit(r.problem, r.state, r.nsteps, analytic=r.state.shape is not None)
                 if slot is None:
                     break
                 resident[slot] = r
@@ -180,7 +182,7 @@ def sequential(requests: List[Request], *, precision: int = E.FP64, stream=None)
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
-        s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream)
+        s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream, analytic=st.shape is not None)
         try:
             s.step(r.nsteps)
             d = s.diagnostics()
@@ -217,7 +219,7 @@ def accuracy(requests: List[Request], *, max_slots: int = 64, hbm_budget: int = 
         slots = {}
         for r in requests:
             pr, st = build(r, E.FP32)
-            slot = batch.admit(pr, st, r.nsteps)
+            slot = batch.admit(pr, st, r.nsteps, analytic=st.shape is not None)
             if slot is None:
                 raise RuntimeError("the accuracy subset must fit one batch")
             slots[r.rid] = slot
@@ -231,7 +233,7 @@ def accuracy(requests: List[Request], *, max_slots: int = 64, hbm_budget: int = 
         batch.close()
     for r in requests:
         pr, st = build(r, E.FP64)
-        s = E.Solver(pr, st, precision=E.FP64, kernel=E.KERNEL_AUTO, stream=stream)
+        s = E.Solver(pr, st, precision=E.FP64, kernel=E.KERNEL_AUTO, stream=stream, analytic=st.shape is not None)
         try:
             s.step(r.nsteps)
             w64, d64 = s.conserved(), s.diagnostics()

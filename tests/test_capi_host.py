@@ -231,3 +231,24 @@ def test_grid_size_limit():
                                 precision=E.FP32)
     assert E.eulbfs_check_params(P32) == ""
     assert 0 < E.eulbfs_workspace_bytes(P32) < E.eulbfs_workspace_bytes(P)
+
+
+@pytest.mark.parametrize("kw, why", [
+    (dict(profile=3), "profile"),
+    (dict(profile=PB.PROFILE_LAYER, axis=2), "axis"),
+    (dict(fl0=1.5), "fl0"),
+    (dict(h0=float("nan")), "finite"),
+])
+def test_bad_shape_rejected_before_touching_the_device(kw, why):
+    """An analytic initial state with an unknown profile, a layer across a
+    third axis, F_l outside [0, 1] or a non-finite value is EINVAL at create,
+    before any device call."""
+    P = _params()
+    with pytest.raises(E.EulbfsError) as ei:
+        E.eulbfs_create(P, shape=PB.Shape(**kw))
+    assert ei.value.code == E.EINVAL and why in str(ei.value)
+
+
+def test_init_struct_layout():
+    assert ct.sizeof(E.eulbfs_shape) == 2 * 4 + 8 * 8 + 8 + 3 * 8
+    assert E.eulbfs_init.shape.offset == 16 and ct.sizeof(E.eulbfs_init) == 24
