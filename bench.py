@@ -45,20 +45,20 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_internal.h, csrc/eulbfs_kernels.hip and
 # build.py).
-COUNTS_FINGERPRINT = "d5936c78371c7fba"
+COUNTS_FINGERPRINT = "6fe7ef257209e135"
 COUNTS = {
-    "fp64/32x8": {"f64": 1237.2, "valu": 1197.9, "hbm": 31890633},
-    "fp64/64x4": {"f64": 1257.8, "valu": 1243.6, "hbm": 31892297},
-    "fp64/16x16": {"f64": 1237.6, "valu": 1190.9, "hbm": 31875401},
-    "fp64/64x8": {"f64": 1128.2, "valu": 1104.1, "hbm": 31878729},
-    "fp64/32x16": {"f64": 1122.8, "valu": 1088.6, "hbm": 31862345},
-    "fp64/32x32": {"f64": 1110.9, "valu": 1076.2, "hbm": 31901572},
-    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1228.9, "hbm": 21815682},
-    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1276.4, "hbm": 21829784},
-    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1219.0, "hbm": 22431550},
-    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1125.3, "hbm": 21814845},
-    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1107.5, "hbm": 21797285},
-    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1053.6, "hbm": 21835461},
+    "fp64/32x8": {"f64": 1237.2, "valu": 1197.9, "hbm": 31889512},
+    "fp64/64x4": {"f64": 1257.8, "valu": 1243.6, "hbm": 31884117},
+    "fp64/16x16": {"f64": 1237.6, "valu": 1190.9, "hbm": 31876437},
+    "fp64/64x8": {"f64": 1128.2, "valu": 1104.1, "hbm": 31880277},
+    "fp64/32x16": {"f64": 1122.8, "valu": 1088.6, "hbm": 31879254},
+    "fp64/32x32": {"f64": 1110.9, "valu": 1076.2, "hbm": 31911549},
+    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1228.9, "hbm": 21810441},
+    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1276.4, "hbm": 21827072},
+    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1219.0, "hbm": 22442812},
+    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1125.3, "hbm": 21815344},
+    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1107.5, "hbm": 21811981},
+    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1053.6, "hbm": 21837840},
 }
 # an FP64 VALU instruction of a wave64 occupies its 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second.  Other VALU
@@ -196,7 +196,7 @@ def hbm_point(name: str, precision: int, steps: int):
 
     pr, st, _ = workload(name)
     stream = torch.cuda.Stream()
-    s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream)
+    s = E.Solver(pr, st, precision=precision, kernel=E.KERNEL_AUTO, stream=stream, analytic=True)
     try:
         sched = s.schedule()
         s.step(8)
@@ -321,6 +321,16 @@ def config_table():
     return {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "configs": rows}
 
 
+def hbm_sweep():
+    """The droplet scaled to 1024^2, 2048^2 and 4096^2 in FP64 and FP32 mode
+    (the working set passes the 256 MB Infinity Cache between 1024^2 and
+    2048^2), and 64 droplets of 512^2 in one FP32 batch."""
+    pts = []
+    for n, steps in ((1024, 200), (2048, 100), (4096, 60)):
+        pts += [hbm_point(f"R{n}", 0, steps), hbm_point(f"R{n}", 1, steps)]
+    return pts + [hbm_batch_point(64, 512, 30)]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -370,8 +380,7 @@ def main():
         print(json.dumps(config_table()), flush=True)
         return
     if args.only_hbm_sweep:
-        print(json.dumps({"hbm_sweep": [hbm_point("R4096", 0, 60), hbm_point("R4096", 1, 60),
-                                        hbm_batch_point(64, 512, 30)]}), flush=True)
+        print(json.dumps({"hbm_sweep": hbm_sweep()}), flush=True)
         return
     pr, st, desc = workload(args.workload)
     precision = 0 if args.precision == "fp64" else 1
@@ -463,7 +472,7 @@ def main():
     if not args.no_hbm_sweep:
         # the 512 x 512 state (34 MB) lives in the 256 MB Infinity Cache: the
         # HBM fraction is measured on working sets well beyond it
-        out["hbm_sweep"] = [hbm_point("R4096", 0, 60), hbm_point("R4096", 1, 60), hbm_batch_point(64, 512, 30)]
+        out["hbm_sweep"] = hbm_sweep()
     if args.serving:
         from paper_2507_03366_amd import serve as S
 
