@@ -451,6 +451,61 @@ def impact_droplet(n: int = 256, we: float = 50.0, re: float = 500.0, U: float =
     return pr, Shape(profile=PROFILE_DROPLET, x0=x0, y0=y0, r0=0.5 * D, t_in=-supercool, v_in=-U).state(pr)
 
 
+# Sec. 3.5 impact cases (SI units): the droplet, the impact speed, the
+# initial and wall temperatures and the contact angles of case (a) and (b)
+IMPACT_CASES = {
+    "a": {"D": 2.84e-3, "U": 0.7, "T_0": -5.0, "T_w": -30.0, "theta_adv": 100.0, "theta_rec": 39.0, "theta_eq": 82.0},
+    "b": {"D": 2.62e-3, "U": 0.44, "T_0": 25.0, "T_w": -30.0, "theta_adv": 105.0, "theta_rec": 70.0, "theta_eq": 70.0},
+}
+# the gas: air at its ratios to the Table 1 water (viscosity 1.8e-5 Pa s,
+# conductivity 0.026 W/(m K), heat capacity 1005 J/(kg K); the paper gives no
+# gas data), at 1/1000 of the liquid density
+AIR = {"mu": 0.0106, "lam": 0.046, "cp": 0.239}
+
+
+def impact_sec35(case: str = "b", T_w: float = None, D0: float = 100.0, U: float = 0.05, nx: int = 400,
+                 ny: int = 200, **kw) -> Tuple[Problem, InitialState]:
+    """Sec. 3.5: a water droplet (Table 1 properties) of diameter D0 cells
+    moving down at U onto a cold no-slip wall with contact-angle hysteresis,
+    on the paper's 400 x 200 grid, walls adiabatic elsewhere, the surface force
+    on the unfrozen part only.  Lattice map: rho_l = C_p,l = 1, T_m - T_w -> 1;
+    Re = rho U D/mu, We = rho U^2 D/sigma and Pr = mu C_p/lambda of the case set
+    the lattice viscosity, surface tension and conductivity; Ste = C_p (T_m -
+    T_w)/L; the solid keeps the Table 1 ratios; the gas is AIR.  T_w (deg C)
+    overrides the case's wall temperature (Table 7 varies it)."""
+    c = IMPACT_CASES[case]
+    m = TABLE1
+    rho_l, rho_s = m["rho"]
+    cp_l, cp_s = m["cp"]
+    lam_l, lam_s = m["lam"]
+    mu_l, sigma_l = 0.0017, 0.076  # Table 1
+    Tw = c["T_w"] if T_w is None else T_w
+    dT = m["T_m"] - Tw
+    Re = rho_l * c["U"] * c["D"] / mu_l
+    We = rho_l * c["U"] ** 2 * c["D"] / sigma_l
+    Pr = mu_l * cp_l / lam_l
+    nu = U * D0 / Re
+    sigma = U * U * D0 / We
+    lam = nu / Pr
+    pr = Problem(
+        nx=nx, ny=ny, rho=(rho_s / rho_l, 1.0, RHO_G), mu=(nu, nu, AIR["mu"] * nu),
+        lam=(lam * lam_s / lam_l, lam, AIR["lam"] * lam), cp=(cp_s / cp_l, 1.0, AIR["cp"]),
+        latent=m["latent"] / (cp_l * dT), sigma=sigma, mobility=ch_mobility(sigma), surf_model=1,
+        walls={"x-": Wall(), "x+": Wall(), "y+": Wall(),
+               "y-": Wall(NOSLIP, DIRICHLET, -1.0, c["theta_eq"], c["theta_adv"], c["theta_rec"])},
+    ).replace(**kw)
+    T0 = (c["T_0"] - m["T_m"]) / dT
+    sh = Shape(profile=PROFILE_DROPLET, x0=0.5 * pr.nx * pr.dx, y0=0.5 * D0 + 2.0 * pr.xi, r0=0.5 * D0,
+               t_in=T0, t_out=T0, v_in=-U)
+    return pr, sh.state(pr)
+
+
+def impact_time(case: str, t_seconds: float, D0: float = 100.0, U: float = 0.05) -> float:
+    """Lattice time of a physical time of a Sec. 3.5 case (t U / D in both)."""
+    c = IMPACT_CASES[case]
+    return t_seconds * c["U"] / c["D"] * D0 / U
+
+
 CONFIGS = {
     "C1": lambda: conductive_freezing(),
     "C2": lambda: three_phase_stefan(),

@@ -40,3 +40,29 @@ def test_shapes_follow_the_closed_forms():
     assert st.shape.r0 == pytest.approx(16.0) and st.shape.y0 == pytest.approx(0.0, abs=1e-12)
     assert math.isclose(st.C[0, 32 + 15], 0.5 * (1.0 + math.tanh(2.0 * (16.0 - math.hypot(15.5, 0.5)) / pr.xi)),
                         abs_tol=1e-15)
+
+
+def test_impact_case_b_follows_the_text():
+    """The Sec. 3.5 case (b) parameters as printed (fixture
+    tests/golden/impact_sec35.txt), and their dimensionless groups in the
+    lattice problem: Re = 678, We = 6.67 and Pr = 12.8 from the Table 1 water."""
+    import os
+
+    g = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "impact_sec35.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = line.split("=")
+                g[k.strip()] = [float(x) for x in v.split()]
+    c = PB.IMPACT_CASES["b"]
+    assert [c["D"] * 1e3, c["U"], c["T_0"], c["T_w"], c["theta_adv"], c["theta_rec"], c["theta_eq"]] == \
+        pytest.approx(g["case_b"])
+    pr, st = PB.impact_sec35("b")
+    U, D0 = 0.05, 100.0
+    assert U * D0 / pr.mu[1] == pytest.approx(1000 * 0.44 * 2.62e-3 / 0.0017)
+    assert U * U * D0 / pr.sigma == pytest.approx(1000 * 0.44 ** 2 * 2.62e-3 / 0.076)
+    assert pr.mu[1] / pr.lam[1] == pytest.approx(0.0017 * 4210 / 0.56)
+    assert 1.0 / pr.latent == pytest.approx(4210 * 30 / 334000)
+    assert st.T.max() == pytest.approx(25.0 / 30.0) and st.v.min() == pytest.approx(-U)
+    assert PB.impact_time("b", 0.015) == pytest.approx(0.015 * 0.44 / 2.62e-3 * D0 / U)
