@@ -259,3 +259,31 @@ def test_batch_tile_choice_rejects_unknown_values():
         assert sc["next_tile"] == E.BATCH_TILE_32x16 and sc["pairs"] == 0 and sc["ticks_timed"] == [0, 0]
     finally:
         b.close()
+
+
+def test_unstable_request_is_reported_and_isolated():
+    """A request whose state holds a non-finite value runs in a batch beside a
+    healthy one: its diagnostics report EULBFS_EUNSTABLE once it finishes, and
+    the healthy request ends bitwise where it ends alone."""
+    import torch
+
+    pr, st = PB.static_droplet(n=64, R=16, sigma=0.015625)
+    bad = PB.InitialState(T=st.T.copy(), Fl=st.Fl.copy(), C=st.C.copy(), u=st.u.copy(), v=st.v.copy(),
+                          p=st.p.copy())
+    bad.C[20, 30] = np.nan
+    b = E.Batch(1 << 27, 4, precision=E.FP64, stream=torch.cuda.Stream())
+    try:
+        s_good = b.admit(pr, st, 60)
+        s_bad = b.admit(pr, bad, 60)
+        while len(b.poll()) < 2:
+            b.tick(20)
+        with pytest.raises(E.EulbfsError) as ei:
+            b.diagnostics(s_bad)
+        assert ei.value.code == E.EUNSTABLE and "non-finite" in str(ei.value)
+        d = b.diagnostics(s_good)
+        assert d["nonfinite"] == 0 and d["steps"] == 60
+        w_good = b.conserved(s_good)
+    finally:
+        b.close()
+    alone, _ = _run_batch([(pr, st)], [60], tick=20)
+    assert np.array_equal(alone[0], w_good)
