@@ -401,7 +401,9 @@ int eulbfs_batch_release(eulbfs_batch_t b, int32_t slot);
  * same steps with different shapes give a paired sample of their time ratio.
  * Until the first pair the ticks alternate between the shapes; then a tick
  * runs the shape that the running geometric mean of the paired ratios
- * favours, and every EULBFS_BATCH_EXPLORE-th tick the other one.  The fixed
+ * favours, and every EULBFS_BATCH_EXPLORE-th tick the other one (a mix that
+ * yields no pair within 4 * EULBFS_BATCH_EXPLORE timed ticks of each shape is
+ * judged by the summed time per cell-step of each shape instead).  The fixed
  * values pin one shape.  Every shape gives the same bits.  EULBFS_EINVAL for
  * another value. */
 #define EULBFS_BATCH_TILE_AUTO 0

@@ -1318,12 +1318,22 @@ void batch_progress(eulbfs_batch* b, bool wait)
 // ticks of the same work has been timed on the two shapes, alternate; then
 // the shape the paired ratios favour, with every EULBFS_BATCH_EXPLORE-th
 // tick on the other.  The time of a tick depends on its requests far more
-// than on its tile, so only ticks of the same work are compared.
+// than on its tile, so only ticks of the same work are compared; a mix that
+// yields no pair within 32 ticks of each shape is judged by its summed
+// times instead.
 int batch_pick_tile(const eulbfs_batch* b)
 {
     if (b->tile_mode != EULBFS_BATCH_TILE_AUTO) return b->tile_mode - 1;
-    if (b->pairs == 0) return (int)(b->tick & 1);
-    const int best = b->log_ratio < 0.0 ? 1 : 0;
+    int best;
+    if (b->pairs > 0) {
+        best = b->log_ratio < 0.0 ? 1 : 0;
+    } else if (b->tile_ticks[0] >= 4 * EULBFS_BATCH_EXPLORE && b->tile_ticks[1] >= 4 * EULBFS_BATCH_EXPLORE) {
+        // a mix that never repeats a tick's work: fall back on the time per
+        // cell-step summed over all timed ticks of each shape
+        best = b->tile_ms[1] * b->tile_cells[0] < b->tile_ms[0] * b->tile_cells[1] ? 1 : 0;
+    } else {
+        return (int)(b->tick & 1);
+    }
     return b->tick % EULBFS_BATCH_EXPLORE == EULBFS_BATCH_EXPLORE - 1 ? 1 - best : best;
 }
 

@@ -287,3 +287,27 @@ def test_unstable_request_is_reported_and_isolated():
         b.close()
     alone, _ = _run_batch([(pr, st)], [60], tick=20)
     assert np.array_equal(alone[0], w_good)
+
+
+def test_batch_tile_choice_without_paired_ticks():
+    """Ticks that never repeat their work (the step count changes every tick)
+    give no paired sample: the choice alternates for 32 timed ticks of each
+    shape, then follows the summed time per cell-step, with every eighth tick
+    on the other shape."""
+    import torch
+
+    pr, st = PB.static_droplet(n=128, R=32, sigma=0.015625)
+    b = E.Batch(1 << 28, 4, precision=E.FP32, stream=torch.cuda.Stream())
+    try:
+        b.admit(pr, st, 100000)
+        for k in range(72):
+            b.tick(3 + k % 5 + (k // 5) % 2)  # consecutive ticks always differ
+        torch.cuda.synchronize()
+        sc = b.schedule()
+        assert sc["pairs"] == 0 and min(sc["ticks_timed"]) >= 32
+        ns = sc["ns_per_cell_step"]
+        best = E.BATCH_TILE_64x8 if ns[1] < ns[0] else E.BATCH_TILE_32x16
+        other = E.BATCH_TILE_32x16 + E.BATCH_TILE_64x8 - best
+        assert sc["next_tile"] == (other if 72 % 8 == 7 else best)
+    finally:
+        b.close()
