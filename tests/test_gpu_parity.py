@@ -371,3 +371,30 @@ def test_two_phase_neumann_on_gpu(oracle):
     _, _, d = _parity_run(oracle, pr, st, 8000)
     k = A.neumann_two_phase_k(1.0 / 250.0, 1.0 / 250.0, 0.4, 0.4)
     assert abs(d["solid"] / pr.ny - 2.0 * k * (0.4 * 8000 * pr.dt) ** 0.5) < 0.1
+
+
+def test_solvers_on_concurrent_streams_are_independent():
+    """Two solvers on two created streams, their steps enqueued alternately
+    so that their launches overlap on the device, end bitwise where each ends
+    alone: handles share no device state."""
+    import torch
+
+    cases = [PB.static_droplet(n=128, R=32, sigma=0.015625), PB.film_freezing(n=96)]
+    alone = []
+    for pr, st in cases:
+        s = E.Solver(pr, st, kernel=E.KERNEL_AUTO, stream=torch.cuda.Stream())
+        try:
+            s.run(240)
+            alone.append(s.conserved())
+        finally:
+            s.close()
+    solvers = [E.Solver(pr, st, kernel=E.KERNEL_AUTO, stream=torch.cuda.Stream()) for pr, st in cases]
+    try:
+        for _ in range(30):
+            for s in solvers:
+                s.step(8)
+        for s, ref in zip(solvers, alone):
+            assert np.array_equal(s.conserved(), ref)
+    finally:
+        for s in solvers:
+            s.close()
