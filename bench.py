@@ -424,13 +424,14 @@ def main():
     hbm_gbs = alg_bytes_per_launch / (avg_launch_us * 1e-6) / 1e9
     fp = kernel_fingerprint()
     ckey = f"{args.precision}/{sched[1]}x{sched[2]}"
-    counts = COUNTS.get(ckey) if (fp == COUNTS_FINGERPRINT and sched[0] == E.KERNEL_FUSED) else None
+    uniform = pr.x_width is None and pr.y_width is None  # the counts are of the uniform-mesh kernels
+    counts = COUNTS.get(ckey) if (fp == COUNTS_FINGERPRINT and sched[0] == E.KERNEL_FUSED and uniform) else None
     if counts:
         flop_cell, peak_tflops = flop_peak(counts)
         flop_per_launch = flop_cell * cells
         tflops = flop_per_launch / (avg_launch_us * 1e-6) / 1e12
         issue = counts["valu"] / 64 * cells / (avg_launch_us * 1e-6) / VALU_ISSUE_PEAK
-    else:  # the counters were taken on other kernel sources or another kernel
+    else:  # the counters were taken on other kernel sources or another kernel (or mesh kind)
         flop_cell = peak_tflops = flop_per_launch = tflops = issue = None
     traffic = counts["hbm"] if (counts and args.workload == "C4") else None
     out = {

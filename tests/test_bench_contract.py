@@ -67,4 +67,6 @@ def test_bench_stretched_workload():
     assert "stretched mesh" in d["config"]["workload"] and d["value"] > 0
     assert d["config"]["schedule"] == {"kernel": "fused", "tile": "32x16"}
     assert d["diagnostics_after"]["nonfinite"] == 0
+    # the counted operations are of the uniform-mesh kernel: none for this one
+    assert d["roofline"]["flop_per_cell_stage"] is None and d["roofline"]["traffic"] is None
     assert d["cpu_baseline"]["value"] > 0
