@@ -54,10 +54,23 @@ __device__ __forceinline__ void cell_update(const DevParams& P, const StageCoef&
     const Cons<R>& wn = Wnk;
     const double cdt = K.cc * P.dt;
     const double Hnew = K.ca * wn.H + K.cb * Wk.H + cdt * (double)res[0];
-    const R ca = R(K.ca), cb = R(K.cb), cdtr = R(cdt);
-    const R pnew = ca * wn.p + cb * Wk.p + cdtr * res[1];
-    R mxnew = ca * wn.mx + cb * Wk.mx + cdtr * res[2];
-    R mynew = ca * wn.my + cb * Wk.my + cdtr * res[3];
+    // FP32 fields: the stage combination as W^n plus its increment,
+    // W^n + b (W^(k) - W^n) + c dt R (a + b = 1 in every stage), so p and M
+    // are rounded once relative to their value and otherwise only relative to
+    // the (small) increment; a W^n + b W^(k) + c dt R in FP32 rounded three
+    // times relative to the value and let a near-steady field drift
+    R pnew, mxnew, mynew;
+    if constexpr (sizeof(R) == sizeof(float)) {
+        const R cb = R(K.cb), cdtr = R(cdt);
+        pnew = wn.p + (cb * (Wk.p - wn.p) + cdtr * res[1]);
+        mxnew = wn.mx + (cb * (Wk.mx - wn.mx) + cdtr * res[2]);
+        mynew = wn.my + (cb * (Wk.my - wn.my) + cdtr * res[3]);
+    } else {
+        const R ca = R(K.ca), cb = R(K.cb), cdtr = R(cdt);
+        pnew = ca * wn.p + cb * Wk.p + cdtr * res[1];
+        mxnew = ca * wn.mx + cb * Wk.mx + cdtr * res[2];
+        mynew = ca * wn.my + cb * Wk.my + cdtr * res[3];
+    }
     const double Cnew = K.ca * wn.C + K.cb * Wk.C + cdt * (double)res[4];
     // rigid solid: M <- (1 - F_s) M with F_s of the new stage value
     const double Fs_new = solid_fraction<FAST>(P, Hnew, Cnew);

@@ -169,10 +169,8 @@ def test_droplet_fp32_batched_against_fp64():
     middle column) and solid volume every 1000 steps, FP32 mode in a batch
     (as served) against FP64 on its own autotuned solver.  The tip agrees within
     0.5 cell (the serving bar) and the solid volume within 1e-4 relative at every
-    sample; at the end H, the momentum and C within 1e-4 relative L2, and p
-    within n 2^-24: p is a near-steady field of small norm (the Laplace
-    pressure) stored in FP32, whose storage rounding of up to 2^-24 of its
-    value each step adds up over the n steps."""
+    sample; every conserved field within 1e-4 relative L2 at the end (the
+    serving bar, here over 40 000 steps)."""
     import torch
 
     pr, st = PB.static_droplet()
@@ -206,4 +204,4 @@ def test_droplet_fp32_batched_against_fp64():
     assert worst_tip < 0.5
     assert worst_solid <= 1e-4
     for name, e in errs.items():
-        assert e <= (n * 2.0 ** -24 if name == "p" else 1e-4), name
+        assert e <= 1e-4, name
