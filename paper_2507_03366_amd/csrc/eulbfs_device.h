@@ -481,6 +481,11 @@ template <typename R, int LAT, int FAST = 0>
 __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X, R F[5])
 {
     constexpr bool HALF = (FAST & FAST_HALF) != 0, UCP = (FAST & FAST_UCP) != 0;
+    // With one C_p and the D2Q9 h lattice the h weights are the f weights, so
+    // the point sum of w C_p T q over a group e_n = +-1, with T = T_0 - s e_t d_T
+    // at its three points, is C_p (T_0 Q_s - s d_T Q_t) in terms of the sums
+    // Q_s = sum w q and Q_t = sum e_t w q the momentum flux needs anyway.
+    constexpr bool HQ_SUMS = UCP && LAT == 9;
     // old-level face state (text after Eq. 54) -> Eq. (7)
     const R Cf = clamp01(X.M[VC]);
     const R Fsf = clamp01(X.M[VFS]);
@@ -525,20 +530,25 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
             const R eut = et == 0 ? R(0) : (et > 0 ? ut : -ut);
             const R eu = en == 0 ? eut : (et == 0 ? eun : eun + eut);
             const R uu = un * un + ut * ut;
-            const R q = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-            const R rq = rho * q;
-            G[g] += w9 * rq;
-            if (et != 0) Gt[g] += R(et) * w9 * rq;
+            // q = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2 is carried as q23 = (2/3) q =
+            // e.u (2 + 3 e.u) - u^2: two multiply-adds whose constants are an
+            // inline 2 and one scalar 3, where 3 and 4.5 together need a copy
+            // into registers; the weights of every sum of q carry the 3/2
+            const R q23 = eu * (R(2) + R(3) * eu) - uu;
+            const R w9q = R(1.5) * w9;
+            const R rq = rho * q23;
+            G[g] += w9q * rq;
+            if (et != 0) Gt[g] += R(et) * w9q * rq;
             if (en != 0) {
-                Qs[g] += w9 * q;
-                if (et != 0) Qt[g] += R(et) * w9 * q;
+                Qs[g] += w9q * q23;
+                if (et != 0) Qt[g] += R(et) * w9q * q23;
             }
             if (in_hg) {
                 if (en != 0 || et != 0) Ce[g] += wh * C * eu;
-                if (en != 0) {
+                if (en != 0 && !HQ_SUMS) {
                     const R T = et == 0 ? base[VT] : base[VT] - ets * dd[VT];
                     const R cp = UCP ? R(P.cp[0]) : mix<R>(P.cp, Cc, Fsc);
-                    Hq[g] += wh * cp * T * q;
+                    Hq[g] += R(1.5) * wh * cp * T * q23;
                 }
             }
         }
@@ -556,6 +566,11 @@ __device__ __forceinline__ void face_flux(const DevParams& P, const Bases<R>& X,
     // point moments of the star distributions (f^eq-m with the face density, Eq. 33)
     const R SMn = sixth * (X.A[VP] + X.B[VP]) + third * rho_f * (Qs[0] + Qs[1]);
     const R SMt = R(HALF ? 1.0 / 72.0 : 1.0 / 18.0) * (X.db[VP] - X.da[VP]) + third * rho_f * (Qt[0] - Qt[1]);
+    if constexpr (HQ_SUMS) {
+        const R s0 = HALF ? R(P.half_off[0]) : R(1);  // offset scale of the stored d, groups e_n = +-1
+        Hq[0] = R(P.cp[0]) * (X.A[VT] * Qs[0] - s0 * (X.da[VT] * Qt[0]));
+        Hq[1] = R(P.cp[0]) * (X.B[VT] * Qs[1] - s0 * (X.db[VT] * Qt[1]));
+    }
     const R SH = R(P.cpref) * sixth * (X.A[VT] - X.B[VT]) + (Hq[0] - Hq[1]);
     const R SG = R(3) * Q * sixth * (X.A[VMU] - X.B[VMU]) + R(3) * (Ce[0] - Ce[1]);
 
