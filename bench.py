@@ -45,20 +45,20 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_internal.h, csrc/eulbfs_kernels.hip and
 # build.py).
-COUNTS_FINGERPRINT = "5f49e023bfaf3316"
+COUNTS_FINGERPRINT = "4d519b7efe9b08b8"
 COUNTS = {
-    "fp64/32x8": {"f64": 1237.2, "valu": 1197.9, "hbm": 31889493},
-    "fp64/64x4": {"f64": 1257.8, "valu": 1243.6, "hbm": 31884117},
-    "fp64/16x16": {"f64": 1237.6, "valu": 1190.9, "hbm": 31876437},
-    "fp64/64x8": {"f64": 1128.2, "valu": 1104.1, "hbm": 31880277},
-    "fp64/32x16": {"f64": 1122.8, "valu": 1088.6, "hbm": 31879253},
-    "fp64/32x32": {"f64": 1110.9, "valu": 1076.2, "hbm": 31911572},
-    "fp32/32x8": {"f32": 1147.3, "f64": 75.5, "valu": 1230.9, "hbm": 21810437},
-    "fp32/64x4": {"f32": 1151.9, "f64": 87.5, "valu": 1278.4, "hbm": 21828096},
-    "fp32/16x16": {"f32": 1147.3, "f64": 75.8, "valu": 1221.0, "hbm": 22437728},
-    "fp32/64x8": {"f32": 1041.9, "f64": 73.0, "valu": 1127.3, "hbm": 21815328},
-    "fp32/32x16": {"f32": 1040.8, "f64": 69.8, "valu": 1109.5, "hbm": 21812746},
-    "fp32/32x32": {"f32": 987.5, "f64": 65.6, "valu": 1055.6, "hbm": 21837886},
+    "fp64/32x8": {"f64": 1152.7, "valu": 1127.1, "hbm": 31872592},
+    "fp64/64x4": {"f64": 1173.3, "valu": 1173.2, "hbm": 31889237},
+    "fp64/16x16": {"f64": 1153.1, "valu": 1119.8, "hbm": 31870549},
+    "fp64/64x8": {"f64": 1051.9, "valu": 1048.7, "hbm": 31868757},
+    "fp64/32x16": {"f64": 1046.5, "valu": 1033.2, "hbm": 31870421},
+    "fp64/32x32": {"f64": 1038.8, "valu": 1022.5, "hbm": 31917964},
+    "fp32/32x8": {"f32": 1060.3, "f64": 75.5, "valu": 1166.4, "hbm": 21811101},
+    "fp32/64x4": {"f32": 1064.9, "f64": 87.5, "valu": 1213.9, "hbm": 21823957},
+    "fp32/16x16": {"f32": 1060.3, "f64": 75.8, "valu": 1156.5, "hbm": 22452320},
+    "fp32/64x8": {"f32": 963.4, "f64": 73.0, "valu": 1069.1, "hbm": 21809676},
+    "fp32/32x16": {"f32": 962.3, "f64": 69.8, "valu": 1051.3, "hbm": 21805880},
+    "fp32/32x32": {"f32": 913.2, "f64": 65.6, "valu": 1000.5, "hbm": 21831433},
 }
 # an FP64 VALU instruction of a wave64 occupies its 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second.  Other VALU
