@@ -273,6 +273,7 @@ DevParams make_dev(const eulbfs_params* p)
     }
     d.wet_k = p->dx * (4.0 / p->xi);
     d.dx = p->dx;
+    d.inv_dx = 1.0 / p->dx;
     d.inv_2dx = 1.0 / (2.0 * p->dx);
     d.inv_dx2 = 1.0 / (p->dx * p->dx);
     d.delta_t = p->delta_t;

@@ -32,7 +32,7 @@ struct DevParams {
     int c_source;     // C source: 0: (1 - r) dF_s/dt, 1: C (1 - r) dF_s/dt
     int periodic_x, periodic_y;
     int flow[4], heat[4];
-    double dx, inv_2dx, inv_dx2, delta_t, dt;
+    double dx, inv_dx, inv_2dx, inv_dx2, delta_t, dt;
     double rho[3], mu[3], lam[3], cp[3];  // solid, liquid, gas (Eq. 7)
     double latent, T_s, T_l;
     double beta, kappa;  // 12 sigma/xi, 3 xi sigma/2 (Sec. 2.3.1)

@@ -318,6 +318,10 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     // starves the others' loads instead (10-15 % slower), so smaller tiles
     // keep the default.
     constexpr bool PRIO = NT >= 1024;
+    // tiles with a wall face (uniform over the workgroup: interior tiles skip
+    // the per-face test)
+    const bool wall_x = !P.periodic_x && (i0 == 0 || i0 + TX >= P.nx);
+    const bool wall_y = !P.periodic_y && (j0 == 0 || j0 + TY >= P.ny);
     if (PRIO) __builtin_amdgcn_s_setprio(3);
     for (int fp = tid; fp < NFXP + NFY; fp += NT) {
         if (PRIO && fp != tid) {
@@ -350,7 +354,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             X.rho_b = plane_rho<R, RHO>(P, sP, a + 1);
             face_flux<R, LAT, FAST>(P, X, F);
             const int gi = i0 + fi;
-            if (!P.periodic_x) {
+            if (wall_x) {
                 if (gi == 0) wall_face(P, 0, F);
                 else if (gi == P.nx) wall_face(P, 1, F);
             }
@@ -383,7 +387,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
             X.rho_b = plane_rho<R, RHO>(P, sP, a + W2);
             face_flux<R, LAT, FAST>(P, X, F);
             const int gj = j0 + fj;
-            if (!P.periodic_y) {
+            if (wall_y) {
                 if (gj == 0) wall_face(P, 2, F);
                 else if (gj == P.ny) wall_face(P, 3, F);
             }
@@ -414,7 +418,7 @@ __device__ __forceinline__ void stage_tile(const DevParams& P, const StageCoef& 
     const int fl = ty * (TX + 1) + tx;
     const int fb = NFX + ty * TX + tx;
     // Eq. (52) on a Cartesian cell: (1/V) S = 1/width along each direction
-    const R idx = NU ? R(mx(MESH_IW, tx + 2)) : R(1.0 / P.dx);
+    const R idx = NU ? R(mx(MESH_IW, tx + 2)) : R(P.inv_dx);
     const R idy = NU ? R(my(MESH_IW, ty + 2)) : idx;
     R dF[5];
 #pragma unroll
@@ -615,7 +619,7 @@ __global__ void __launch_bounds__(SPLIT_THREADS) k_split_update(DevParams P, Sta
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= P.nx || j >= P.ny) return;
     // Eq. (52) on a Cartesian cell: (1/V) S = 1/width along each direction
-    const R idx = NU ? R(P.mxc[MESH_IW * P.msx + i + NG]) : R(1.0 / P.dx);
+    const R idx = NU ? R(P.mxc[MESH_IW * P.msx + i + NG]) : R(P.inv_dx);
     const R idy = NU ? R(P.myc[MESH_IW * P.msy + j + NG]) : idx;
     const size_t o = (size_t)j * fpitch + i;
     R dF[5];
