@@ -45,20 +45,20 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # valid only for the sources and compile flags with this fingerprint (sha256
 # of csrc/eulbfs_device.h, csrc/eulbfs_internal.h, csrc/eulbfs_kernels.hip and
 # build.py).
-COUNTS_FINGERPRINT = "4d519b7efe9b08b8"
+COUNTS_FINGERPRINT = "faa2f891ed7b98a2"
 COUNTS = {
-    "fp64/32x8": {"f64": 1152.7, "valu": 1127.1, "hbm": 31872592},
-    "fp64/64x4": {"f64": 1173.3, "valu": 1173.2, "hbm": 31889237},
-    "fp64/16x16": {"f64": 1153.1, "valu": 1119.8, "hbm": 31870549},
-    "fp64/64x8": {"f64": 1051.9, "valu": 1048.7, "hbm": 31868757},
-    "fp64/32x16": {"f64": 1046.5, "valu": 1033.2, "hbm": 31870421},
-    "fp64/32x32": {"f64": 1038.8, "valu": 1022.5, "hbm": 31917964},
-    "fp32/32x8": {"f32": 1060.3, "f64": 75.5, "valu": 1166.4, "hbm": 21811101},
-    "fp32/64x4": {"f32": 1064.9, "f64": 87.5, "valu": 1213.9, "hbm": 21823957},
-    "fp32/16x16": {"f32": 1060.3, "f64": 75.8, "valu": 1156.5, "hbm": 22452320},
-    "fp32/64x8": {"f32": 963.4, "f64": 73.0, "valu": 1069.1, "hbm": 21809676},
-    "fp32/32x16": {"f32": 962.3, "f64": 69.8, "valu": 1051.3, "hbm": 21805880},
-    "fp32/32x32": {"f32": 913.2, "f64": 65.6, "valu": 1000.5, "hbm": 21831433},
+    "fp64/32x8": {"f64": 1138.7, "valu": 1103.1, "hbm": 31888981},
+    "fp64/64x4": {"f64": 1159.3, "valu": 1149.5, "hbm": 31880789},
+    "fp64/16x16": {"f64": 1139.1, "valu": 1095.9, "hbm": 31874662},
+    "fp64/64x8": {"f64": 1038.9, "valu": 1016.7, "hbm": 31870549},
+    "fp64/32x16": {"f64": 1033.5, "valu": 1000.3, "hbm": 31871829},
+    "fp64/32x32": {"f64": 1024.8, "valu": 989.6, "hbm": 31918520},
+    "fp32/32x8": {"f32": 1060.3, "f64": 61.5, "valu": 1138.0, "hbm": 21818898},
+    "fp32/64x4": {"f32": 1064.9, "f64": 73.5, "valu": 1186.2, "hbm": 21826080},
+    "fp32/16x16": {"f32": 1060.3, "f64": 61.8, "valu": 1127.9, "hbm": 22431096},
+    "fp32/64x8": {"f32": 964.4, "f64": 59.0, "valu": 1048.2, "hbm": 21811023},
+    "fp32/32x16": {"f32": 963.3, "f64": 55.8, "valu": 1029.9, "hbm": 21807722},
+    "fp32/32x32": {"f32": 913.2, "f64": 51.6, "valu": 974.9, "hbm": 21845505},
 }
 # an FP64 VALU instruction of a wave64 occupies its 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second.  Other VALU
