@@ -854,12 +854,13 @@ int autotune(eulbfs_solver* h, const eulbfs_init* init)
         (void)hipEventDestroy(a);
         return set_err(err, EULBFS_EDEVICE, "autotune: hipEventCreate failed");
     }
-    int best = TILE_32x8, rc = EULBFS_OK;
-    float best_ms = 0.0f;
-    for (int tile = 0; tile < NTILES && rc == EULBFS_OK; ++tile) {
-        h->tile = tile;
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2 && rc == EULBFS_OK; ++rep) {  // best of two
+    // best of three per shape, the shapes taken in turn within each round so
+    // that a drift of the clock during the trials weighs on all of them alike
+    float ms[NTILES] = {};
+    int rc = EULBFS_OK;
+    for (int rep = 0; rep < 3 && rc == EULBFS_OK; ++rep) {
+        for (int tile = 0; tile < NTILES && rc == EULBFS_OK; ++tile) {
+            h->tile = tile;
             rc = enqueue_raw<R>(h, 1);
             float t = 0.0f;
             if (rc == EULBFS_OK &&
@@ -867,13 +868,12 @@ int autotune(eulbfs_solver* h, const eulbfs_init* init)
                  hipEventRecord(b, h->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
                  hipEventElapsedTime(&t, a, b) != hipSuccess))
                 rc = set_err(err, EULBFS_EDEVICE, "autotune: a timed launch failed");
-            if (rc == EULBFS_OK && (rep == 0 || t < ms)) ms = t;
-        }
-        if (rc == EULBFS_OK && (tile == 0 || ms < best_ms)) {
-            best = tile;
-            best_ms = ms;
+            if (rc == EULBFS_OK && (rep == 0 || t < ms[tile])) ms[tile] = t;
         }
     }
+    int best = 0;
+    for (int tile = 1; tile < NTILES; ++tile)
+        if (ms[tile] < ms[best]) best = tile;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc != EULBFS_OK) return rc;
