@@ -47,18 +47,18 @@ VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # build.py).
 COUNTS_FINGERPRINT = "faa2f891ed7b98a2"
 COUNTS = {
-    "fp64/32x8": {"f64": 1138.7, "valu": 1103.1, "hbm": 31888981},
+    "fp64/32x8": {"f64": 1138.7, "valu": 1103.0, "hbm": 31888981},
     "fp64/64x4": {"f64": 1159.3, "valu": 1149.5, "hbm": 31880789},
-    "fp64/16x16": {"f64": 1139.1, "valu": 1095.9, "hbm": 31874662},
-    "fp64/64x8": {"f64": 1038.9, "valu": 1016.7, "hbm": 31870549},
-    "fp64/32x16": {"f64": 1033.5, "valu": 1000.3, "hbm": 31871829},
-    "fp64/32x32": {"f64": 1024.8, "valu": 989.6, "hbm": 31918520},
-    "fp32/32x8": {"f32": 1060.3, "f64": 61.5, "valu": 1138.0, "hbm": 21818898},
-    "fp32/64x4": {"f32": 1064.9, "f64": 73.5, "valu": 1186.2, "hbm": 21826080},
-    "fp32/16x16": {"f32": 1060.3, "f64": 61.8, "valu": 1127.9, "hbm": 22431096},
-    "fp32/64x8": {"f32": 964.4, "f64": 59.0, "valu": 1048.2, "hbm": 21811023},
-    "fp32/32x16": {"f32": 963.3, "f64": 55.8, "valu": 1029.9, "hbm": 21807722},
-    "fp32/32x32": {"f32": 913.2, "f64": 51.6, "valu": 974.9, "hbm": 21845505},
+    "fp64/16x16": {"f64": 1139.0, "valu": 1095.8, "hbm": 31874648},
+    "fp64/64x8": {"f64": 1038.9, "valu": 1016.6, "hbm": 31870549},
+    "fp64/32x16": {"f64": 1033.5, "valu": 1000.3, "hbm": 31871830},
+    "fp64/32x32": {"f64": 1024.8, "valu": 989.6, "hbm": 31918462},
+    "fp32/32x8": {"f32": 1060.3, "f64": 61.4, "valu": 1137.8, "hbm": 21818933},
+    "fp32/64x4": {"f32": 1064.9, "f64": 73.5, "valu": 1186.1, "hbm": 21826072},
+    "fp32/16x16": {"f32": 1060.3, "f64": 61.7, "valu": 1127.8, "hbm": 22437606},
+    "fp32/64x8": {"f32": 964.4, "f64": 59.0, "valu": 1048.1, "hbm": 21810918},
+    "fp32/32x16": {"f32": 963.3, "f64": 55.7, "valu": 1029.9, "hbm": 21807684},
+    "fp32/32x32": {"f32": 913.2, "f64": 51.6, "valu": 974.9, "hbm": 21845504},
 }
 # an FP64 VALU instruction of a wave64 occupies its 16-lane SIMD for 4 cycles:
 # 1024 SIMDs x 2.4 GHz / 4 wave-instructions per second.  Other VALU
